@@ -1,0 +1,26 @@
+"""Compile the FP64 oracle (plain C, gcc) into oracle/liboracle.so.
+
+Built with -O2, no fast-math and no floating-point contraction so that its
+double-precision decisions (hit bins) are plain IEEE operations.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def build(verbose=False):
+    src = os.path.join(HERE, "kf_oracle.c")
+    out = os.path.join(HERE, "liboracle.so")
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-std=c99", "-D_GNU_SOURCE", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", tmp, src, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
