@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the CPU
 baseline timing are the only code allowed to import this package.  It wraps
-`liboracle.so` (plain C, built from kf_oracle.c by `oracle.build`) with numpy
+`liboracle.so` (plain C, built from kf_oracle.c by `oracle.make_lib`) with numpy
 arrays in array-of-structures float64 layout; it shares nothing with the GPU
 library.
 """
@@ -50,7 +50,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            from . import build as _b
+            from . import make_lib as _b
             _b.build()
         _lib = C.CDLL(LIB_PATH)
         _declare(_lib)

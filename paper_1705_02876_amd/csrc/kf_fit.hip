@@ -1,0 +1,303 @@
+// kf_fit.hip -- context, geometry, and the propagate / update / fit entry
+// points of the C ABI (one track per lane, structure-of-arrays in HBM).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "kf_internal.hpp"
+
+using namespace kfd;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+// Coalesced SoA loads/stores of one track's state and packed covariance.
+__device__ __forceinline__ void load_track(const float* __restrict__ st, const float* __restrict__ cv, int64_t ld,
+                                           int64_t i, float s[6], float c[21]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[k] = __builtin_nontemporal_load(st + k * ld + i);
+#pragma unroll
+  for (int k = 0; k < 21; ++k) c[k] = __builtin_nontemporal_load(cv + k * ld + i);
+}
+
+__device__ __forceinline__ void store_track(float* __restrict__ st, float* __restrict__ cv, int64_t ld, int64_t i,
+                                            const float s[6], const float c[21]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(s[k], st + k * ld + i);
+#pragma unroll
+  for (int k = 0; k < 21; ++k) __builtin_nontemporal_store(c[k], cv + k * ld + i);
+}
+
+__global__ void __launch_bounds__(256) propagate_kernel(int64_t n, int64_t ld, float* state, float* cov,
+                                                        const int8_t* __restrict__ charge,
+                                                        const float* __restrict__ r_target, float r_scalar,
+                                                        float z_half, int32_t material_layer, Geom g,
+                                                        int32_t* __restrict__ status) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s[6], c[21];
+  load_track(state, cov, ld, i, s, c);
+  const float a = -static_cast<float>(charge[i]) * kCLight * g.bz;
+  int32_t st = 0;
+  if (material_layer >= 0) {
+    if (!finite6_21(s, c))
+      st = ST_NONFINITE;
+    else
+      st = material(s, c, g.x_over_x0[material_layer], g.eloss_per_x0, g.mass);
+  }
+  if (!st) st = propagate(s, c, a, r_target ? r_target[i] : r_scalar, z_half);
+  if (!st) store_track(state, cov, ld, i, s, c);
+  status[i] = st;
+}
+
+__global__ void __launch_bounds__(256) update_kernel(int64_t n, int64_t ld, float* state, float* cov,
+                                                     const float* __restrict__ hit_pos,
+                                                     const float* __restrict__ hit_cov, int64_t ldh,
+                                                     float* __restrict__ chi2, int32_t* __restrict__ status,
+                                                     int chi2_only) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s[6], c[21], m[3], v[6];
+  load_track(state, cov, ld, i, s, c);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m[k] = hit_pos[k * ldh + i];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = hit_cov[k * ldh + i];
+  float c2 = 0.f;
+  int32_t st;
+  if (!finite6_21(s, c)) {
+    st = ST_NONFINITE;
+  } else if (chi2_only) {
+    float ri[6], r[3];
+    st = chi2_of(s, c, m, v, ri, r, c2);
+  } else {
+    st = update(s, c, m, v, c2);
+    if (!st) store_track(state, cov, ld, i, s, c);
+  }
+  chi2[i] = st ? 0.f : c2;
+  status[i] = st;
+}
+
+// Features of a prediction for the learned search window (see kfmi.h):
+// q/pT, cot(theta), z/z_half, sin(phi_dir - phi_pos), r_from/100, r_to/100,
+// log sigma_rphi, log sigma_z of the predicted position; targets are the
+// tangential and z offsets of the track's own hit from the prediction.
+__device__ __forceinline__ void emit_residual(float* __restrict__ out, int64_t ldr, int64_t row, const float s[6],
+                                              const float c[21], float q, float r_from, float r_to, float zh,
+                                              const float m[3]) {
+  const float ipt = __frsqrt_rn(s[3] * s[3] + s[4] * s[4]);
+  const float ir = __frsqrt_rn(s[0] * s[0] + s[1] * s[1]);
+  const float tx = -s[1] * ir, ty = s[0] * ir;  // tangential unit vector
+  const float ctt = tx * tx * c[0] + 2.f * tx * ty * c[1] + ty * ty * c[2];
+  const float f[KF_RES_FEATURES + 2] = {
+      q * ipt,
+      s[5] * ipt,
+      s[2] / zh,
+      (s[0] * s[4] - s[1] * s[3]) * ipt * ir,
+      r_from * 0.01f,
+      r_to * 0.01f,
+      0.5f * logf(fmaxf(ctt, 1e-30f)),
+      0.5f * logf(fmaxf(c[5], 1e-30f)),
+      tx * (m[0] - s[0]) + ty * (m[1] - s[1]),
+      m[2] - s[2],
+  };
+#pragma unroll
+  for (int k = 0; k < KF_RES_FEATURES + 2; ++k) out[k * ldr + row] = f[k];
+}
+
+__global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const float* state_in,
+                                                  const float* cov_in, const int8_t* __restrict__ charge,
+                                                  const int32_t* __restrict__ hit_idx, int64_t ld_idx,
+                                                  const float* __restrict__ hit_pos,
+                                                  const float* __restrict__ hit_cov, int64_t ldh, float* state_out,
+                                                  float* cov_out, float* __restrict__ chi2_out,
+                                                  int32_t* __restrict__ nhits_out, int32_t* __restrict__ status_out,
+                                                  Geom g, float* __restrict__ res, int64_t ldr) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int L = g.n_layers;
+  float s[6], c[21];
+  load_track(state_in, cov_in, ld, i, s, c);
+  const float qf = static_cast<float>(charge[i]);
+  const float a = -qf * kCLight * g.bz;
+  int last = -1;
+  for (int l = 0; l < L; ++l)
+    if (hit_idx[l * ld_idx + i] >= 0) last = l;
+  float chi2 = 0.f;
+  int32_t nh = 0, st = 0;
+  if (res) {
+    for (int l = 1; l < L; ++l)
+#pragma unroll
+      for (int k = 0; k < KF_RES_FEATURES + 2; ++k) res[k * ldr + i * (L - 1) + (l - 1)] = NAN;
+  }
+  float r_from = 0.f;
+  for (int l = 0; l <= last; ++l) {
+    float s2[6], c2[21];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s2[k] = s[k];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) c2[k] = c[k];
+    st = propagate(s2, c2, a, g.r[l], 0.f);
+    if (st) break;
+    const int32_t h = hit_idx[l * ld_idx + i];
+    if (h >= 0) {
+      float m[3], v[6], dc2;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) m[k] = hit_pos[k * ldh + h];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[k] = hit_cov[k * ldh + h];
+      if (res && l >= 1) emit_residual(res, ldr, i * (L - 1) + (l - 1), s2, c2, qf, r_from, g.r[l], g.z_half[l], m);
+      st = update(s2, c2, m, v, dc2);
+      if (st) break;
+      chi2 += dc2;
+      nh += 1;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = s2[k];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) c[k] = c2[k];
+    r_from = g.r[l];
+    if (l < last) {
+      st = material(s2, c2, g.x_over_x0[l], g.eloss_per_x0, g.mass);
+      if (st) break;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s[k] = s2[k];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) c[k] = c2[k];
+    }
+  }
+  store_track(state_out, cov_out, ld, i, s, c);
+  chi2_out[i] = chi2;
+  nhits_out[i] = nh;
+  status_out[i] = st;
+}
+
+}  // namespace
+
+namespace kfh {
+
+int32_t set_error(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int32_t enter(kf_ctx* ctx) {
+  if (!ctx) return set_error(KF_ERR_INVALID_ARG, "null context");
+  return check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+}
+
+}  // namespace kfh
+
+using kfh::set_error;
+
+extern "C" {
+
+const char* kf_last_error(void) { return g_last_error.c_str(); }
+
+int32_t kf_ctx_create(kf_ctx** out, int32_t device) {
+  if (!out) return set_error(KF_ERR_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  int count = 0;
+  if (int32_t rc = kfh::check_hip(hipGetDeviceCount(&count), "hipGetDeviceCount")) return rc;
+  if (device < 0 || device >= count) return set_error(KF_ERR_INVALID_ARG, "device %d out of range", device);
+  hipDeviceProp_t prop;
+  if (int32_t rc = kfh::check_hip(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties")) return rc;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_error(KF_ERR_UNSUPPORTED, "device %d is %s, this library is built for gfx950", device,
+                     prop.gcnArchName);
+  kf_ctx* c = new kf_ctx();
+  c->device = device;
+  c->num_cus = prop.multiProcessorCount;
+  *out = c;
+  return KF_OK;
+}
+
+void kf_ctx_destroy(kf_ctx* ctx) { delete ctx; }
+
+int32_t kf_set_geometry(kf_ctx* ctx, const kf_geometry* g) {
+  if (!ctx || !g) return set_error(KF_ERR_INVALID_ARG, "null argument");
+  if (g->n_layers < 1 || g->n_layers > KF_MAX_LAYERS)
+    return set_error(KF_ERR_GEOMETRY, "n_layers %d not in [1, %d]", g->n_layers, KF_MAX_LAYERS);
+  for (int l = 0; l < g->n_layers; ++l) {
+    if (!(g->r[l] > 0.f) || !std::isfinite(g->r[l])) return set_error(KF_ERR_GEOMETRY, "r[%d] not positive", l);
+    if (l > 0 && !(g->r[l] > g->r[l - 1])) return set_error(KF_ERR_GEOMETRY, "radii not strictly increasing");
+    if (!(g->z_half[l] > 0.f)) return set_error(KF_ERR_GEOMETRY, "z_half[%d] not positive", l);
+    if (!(g->x_over_x0[l] >= 0.f)) return set_error(KF_ERR_GEOMETRY, "x_over_x0[%d] negative", l);
+  }
+  if (!std::isfinite(g->bz) || !(g->mass > 0.f) || !(g->eloss_per_x0 >= 0.f))
+    return set_error(KF_ERR_GEOMETRY, "bad field, mass or energy loss");
+  ctx->geom = *g;
+  Geom& d = ctx->dgeom;
+  std::memset(&d, 0, sizeof d);
+  d.n_layers = g->n_layers;
+  for (int l = 0; l < KF_MAX_LAYERS; ++l) {
+    d.r[l] = g->r[l];
+    d.z_half[l] = g->z_half[l];
+    d.x_over_x0[l] = g->x_over_x0[l];
+  }
+  d.bz = g->bz;
+  d.eloss_per_x0 = g->eloss_per_x0;
+  d.mass = g->mass;
+  ctx->has_geometry = true;
+  return KF_OK;
+}
+
+int32_t kf_propagate_to_r(kf_ctx* ctx, int64_t n, int64_t ld, float* state, float* cov, const int8_t* charge,
+                          const float* r_target, float r_scalar, float z_half, int32_t material_layer,
+                          int32_t* status, void* stream) {
+  if (int32_t rc = kfh::enter(ctx)) return rc;
+  if (!ctx->has_geometry) return set_error(KF_ERR_GEOMETRY, "no geometry set");
+  if (n < 0 || ld < n) return set_error(KF_ERR_INVALID_ARG, "n=%lld ld=%lld", (long long)n, (long long)ld);
+  if (n == 0) return KF_OK;
+  if (!state || !cov || !charge || !status) return set_error(KF_ERR_INVALID_ARG, "null array");
+  if (!r_target && !(r_scalar > 0.f)) return set_error(KF_ERR_INVALID_ARG, "r_scalar must be > 0");
+  if (material_layer >= ctx->geom.n_layers) return set_error(KF_ERR_INVALID_ARG, "material_layer out of range");
+  propagate_kernel<<<kfh::grid_for(n, 256), 256, 0, kfh::stream_of(stream)>>>(
+      n, ld, state, cov, charge, r_target, r_scalar, z_half, material_layer, ctx->dgeom, status);
+  return kfh::check_hip(hipGetLastError(), "propagate_kernel launch");
+}
+
+int32_t kf_update(kf_ctx* ctx, int64_t n, int64_t ld, float* state, float* cov, const float* hit_pos,
+                  const float* hit_cov, int64_t ldh, float* chi2, int32_t* status, uint32_t flags, void* stream) {
+  if (int32_t rc = kfh::enter(ctx)) return rc;
+  if (n < 0 || ld < n || ldh < n)
+    return set_error(KF_ERR_INVALID_ARG, "n=%lld ld=%lld ldh=%lld", (long long)n, (long long)ld, (long long)ldh);
+  if (flags & ~KF_UPDATE_CHI2_ONLY) return set_error(KF_ERR_INVALID_ARG, "unknown flags %u", flags);
+  if (n == 0) return KF_OK;
+  if (!state || !cov || !hit_pos || !hit_cov || !chi2 || !status) return set_error(KF_ERR_INVALID_ARG, "null array");
+  update_kernel<<<kfh::grid_for(n, 256), 256, 0, kfh::stream_of(stream)>>>(
+      n, ld, state, cov, hit_pos, hit_cov, ldh, chi2, status, (flags & KF_UPDATE_CHI2_ONLY) ? 1 : 0);
+  return kfh::check_hip(hipGetLastError(), "update_kernel launch");
+}
+
+int32_t kf_fit(kf_ctx* ctx, const kf_fit_args* a) {
+  if (int32_t rc = kfh::enter(ctx)) return rc;
+  if (!a) return set_error(KF_ERR_INVALID_ARG, "null args");
+  if (!ctx->has_geometry) return set_error(KF_ERR_GEOMETRY, "no geometry set");
+  const int L = ctx->geom.n_layers;
+  if (a->n < 0 || a->ld < a->n || a->ld_idx < a->n || a->ldh < 0)
+    return set_error(KF_ERR_INVALID_ARG, "bad sizes");
+  if (a->flags & ~KF_FIT_EMIT_RESIDUALS) return set_error(KF_ERR_INVALID_ARG, "unknown flags %u", a->flags);
+  const bool emit = (a->flags & KF_FIT_EMIT_RESIDUALS) != 0;
+  if (emit && (!a->residual_out || L < 2 || a->ld_res < a->n * (L - 1)))
+    return set_error(KF_ERR_INVALID_ARG, "residual_out missing or ld_res < n * (n_layers - 1)");
+  if (a->n == 0) return KF_OK;
+  if (!a->state_in || !a->cov_in || !a->charge || !a->hit_idx || !a->state_out || !a->cov_out || !a->chi2_out ||
+      !a->nhits_out || !a->status_out)
+    return set_error(KF_ERR_INVALID_ARG, "null array");
+  fit_kernel<<<kfh::grid_for(a->n, 256), 256, 0, kfh::stream_of(a->stream)>>>(
+      a->n, a->ld, a->state_in, a->cov_in, a->charge, a->hit_idx, a->ld_idx, a->hit_pos, a->hit_cov, a->ldh,
+      a->state_out, a->cov_out, a->chi2_out, a->nhits_out, a->status_out, ctx->dgeom,
+      emit ? a->residual_out : nullptr, a->ld_res);
+  return kfh::check_hip(hipGetLastError(), "fit_kernel launch");
+}
+
+}  // extern "C"

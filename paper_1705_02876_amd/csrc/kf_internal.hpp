@@ -1,0 +1,38 @@
+// kf_internal.hpp -- host-side context and helpers shared by the library's
+// translation units (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/kfmi.h"
+#include "kf_device.hpp"
+
+struct kf_ctx {
+  int device = 0;
+  bool has_geometry = false;
+  kf_geometry geom{};
+  kfd::Geom dgeom{};
+  int num_cus = 0;
+};
+
+namespace kfh {
+
+int32_t set_error(int32_t code, const char* fmt, ...);
+
+inline int32_t check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) return set_error(KF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return KF_OK;
+}
+
+// Make ctx's device current for this host thread.
+int32_t enter(kf_ctx* ctx);
+
+inline hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline unsigned grid_for(int64_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
+
+}  // namespace kfh

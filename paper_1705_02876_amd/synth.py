@@ -319,37 +319,59 @@ class FitProblem:
     extra: dict = field(default_factory=dict)
 
 
-def make_fit_problem(n, det: Detector, seed, p_miss=0.0, min_hits=0, smear=True, prior_at_truth=False,
-                     prior_sigma_scale=1.0):
-    """Tracks for the fit: hits at the crossed layers, prior = truth + N(0, C0) at the vertex.
+FIT_CHUNK = 131072
 
-    Tracks with fewer than `min_hits` hits are re-drawn until every track qualifies.
-    Hits are stored layer-major, in track order within each layer (coalesced gathers).
-    """
-    rng = np.random.Generator(np.random.PCG64(seed))
-    L = det.n_layers
-    sims = []
+
+def _fit_chunk(seed, chunk_id, n, det, p_miss, min_hits, smear, prior_at_truth, prior_sigma_scale):
+    """One chunk of fit tracks with its own random stream (seed, chunk_id)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(chunk_id)])))
     need = n
-    keep_q, keep_mom0 = [], []
-    keep_hp, keep_has, keep_tp, keep_tm = [], [], [], []
+    parts = []
     while need > 0:
         m = int(need * 1.02) + 16
         s = simulate(rng, m, det, p_miss=p_miss, smear=smear)
         nh = s["has_hit"].sum(axis=0)
         good = np.nonzero(nh >= max(min_hits, 1))[0][:need]
-        keep_q.append(s["q"][good])
-        keep_mom0.append(s["mom0"][good])
-        keep_hp.append(s["hit_pos"][:, good])
-        keep_has.append(s["has_hit"][:, good])
-        keep_tp.append(s["true_pos"][:, good])
-        keep_tm.append(s["true_mom"][:, good])
+        parts.append((s["q"][good], s["mom0"][good], s["hit_pos"][:, good], s["has_hit"][:, good],
+                      s["true_pos"][:, good], s["true_mom"][:, good]))
         need -= good.size
-    q = np.concatenate(keep_q)
-    mom0 = np.concatenate(keep_mom0)
-    hp = np.concatenate(keep_hp, axis=1)
-    has = np.concatenate(keep_has, axis=1)
-    tp = np.concatenate(keep_tp, axis=1)
-    tm = np.concatenate(keep_tm, axis=1)
+    q, mom0, hp, has, tp, tm = [np.concatenate([p_[k] for p_ in parts], axis=0 if k < 2 else 1) for k in range(6)]
+    sig = fit_prior_sigmas(mom0) * prior_sigma_scale
+    truth0 = np.concatenate([np.zeros((n, 3)), mom0], axis=1)
+    state0 = truth0.copy() if prior_at_truth else truth0 + rng.standard_normal((n, 6)) * sig
+    return q, mom0, hp, has, tp, tm, sig, state0
+
+
+def make_fit_problem(n, det: Detector, seed, p_miss=0.0, min_hits=0, smear=True, prior_at_truth=False,
+                     prior_sigma_scale=1.0, workers=None):
+    """Tracks for the fit: hits at the crossed layers, prior = truth + N(0, C0) at the vertex.
+
+    Tracks with fewer than `min_hits` hits are re-drawn until every track qualifies.
+    Hits are stored layer-major, in track order within each layer (coalesced gathers).
+    Generation runs in chunks of FIT_CHUNK tracks with independent random streams
+    derived from (seed, chunk index), on a thread pool; the result depends only on
+    (n, seed), not on the number of workers.
+    """
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    L = det.n_layers
+    sizes = [min(FIT_CHUNK, n - k) for k in range(0, n, FIT_CHUNK)] or [0]
+    args = [(seed, i, sz, det, p_miss, min_hits, smear, prior_at_truth, prior_sigma_scale)
+            for i, sz in enumerate(sizes)]
+    nw = workers or min(8, os.cpu_count() or 1, len(args))
+    if nw > 1:
+        with ThreadPoolExecutor(nw) as ex:
+            chunks = list(ex.map(lambda a: _fit_chunk(*a), args))
+    else:
+        chunks = [_fit_chunk(*a) for a in args]
+    q = np.concatenate([c[0] for c in chunks])
+    mom0 = np.concatenate([c[1] for c in chunks])
+    hp = np.concatenate([c[2] for c in chunks], axis=1)
+    has = np.concatenate([c[3] for c in chunks], axis=1)
+    tp = np.concatenate([c[4] for c in chunks], axis=1)
+    tm = np.concatenate([c[5] for c in chunks], axis=1)
+    sig = np.concatenate([c[6] for c in chunks])
+    state0 = np.concatenate([c[7] for c in chunks])
     hit_idx = np.full((L, n), -1, dtype=np.int32)
     counts = has.sum(axis=1)
     offs = np.concatenate([[0], np.cumsum(counts)])
@@ -361,14 +383,9 @@ def make_fit_problem(n, det: Detector, seed, p_miss=0.0, min_hits=0, smear=True,
         hit_pos[offs[l]:offs[l + 1]] = hp[l, idx]
     hit_cov = hit_cov_packed(det, H)
     truth0 = np.concatenate([np.zeros((n, 3)), mom0], axis=1)
-    sig = fit_prior_sigmas(mom0) * prior_sigma_scale
     cov0 = np.zeros((n, 6, 6))
     for i in range(6):
         cov0[:, i, i] = sig[:, i] ** 2
-    if prior_at_truth:
-        state0 = truth0.copy()
-    else:
-        state0 = truth0 + rng.standard_normal((n, 6)) * sig
     last = np.where(has.any(axis=0), L - 1 - np.argmax(has[::-1], axis=0), -1)
     ar = np.arange(n)
     truth_last = np.concatenate([tp[last, ar], tm[last, ar]], axis=1)

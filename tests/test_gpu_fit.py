@@ -1,0 +1,229 @@
+"""GPU parity of propagate, update and fit against the FP64 oracle (through the C ABI).
+
+Tolerances (kfutil): state 1e-4 relative, chi2 1e-3, covariance 1e-3 of
+sqrt(C_ii C_jj).  Both sides see the same float32-rounded inputs; the oracle
+computes in double precision.
+"""
+import numpy as np
+import pytest
+
+from paper_1705_02876_amd import synth as S
+
+from kfutil import (check_chi2, check_cov, check_params, fit_inputs_gpu, from_soa_cov, from_soa_state, oracle_fit_on_f32,
+                    rounded, soa_cov, soa_state, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1705_02876_amd import kfmi
+    assert torch.cuda.is_available()
+    c = kfmi.Context(0)
+    yield c
+    c.close()
+
+
+def _fit_gpu(ctx, fp, pad=0, residuals=False):
+    import torch
+    d = fit_inputs_gpu(fp, pad)
+    ld = d["ld"]
+    so = torch.empty(6, ld, dtype=torch.float32, device="cuda")
+    co = torch.empty(21, ld, dtype=torch.float32, device="cuda")
+    chi2 = torch.empty(ld, dtype=torch.float32, device="cuda")
+    nh = torch.empty(ld, dtype=torch.int32, device="cuda")
+    st = torch.empty(ld, dtype=torch.int32, device="cuda")
+    res = None
+    if residuals:
+        L = fp.hit_idx.shape[0]
+        res = torch.empty(10, d["n"] * (L - 1), dtype=torch.float32, device="cuda")
+    ctx.kf_fit(d["state"], d["cov"], d["q"], d["hidx"], d["hpos"], d["hcov"], so, co, chi2, nh, st,
+               residual_out=res, n=d["n"])
+    torch.cuda.synchronize()
+    n = d["n"]
+    out = (from_soa_state(so, n), from_soa_cov(co, n), chi2.cpu().numpy()[:n].astype(np.float64),
+           nh.cpu().numpy()[:n], st.cpu().numpy()[:n])
+    if residuals:
+        return out, res.cpu().numpy()
+    return out
+
+
+@pytest.mark.parametrize("which,n,pad", [("small", 1000, 0), ("full", 20037, 5), ("full", 1, 0), ("full", 255, 1)])
+def test_fit_parity(ctx, orc, which, n, pad):
+    det = S.detector_small() if which == "small" else S.detector_full()
+    det32 = det.as_float32()
+    fp = S.make_fit_problem(n, det, 100 + n, p_miss=0.0 if which == "small" else 0.05,
+                            min_hits=0 if which == "small" else 6)
+    ctx.kf_set_geometry(det32)
+    gs, gc, gchi, gnh, gst = _fit_gpu(ctx, fp, pad)
+    os_, oc, ochi, onh, ost = oracle_fit_on_f32(orc, det32, fp)
+    print(f"[fit parity] {which} n={n}: status gpu {np.bincount(gst)} oracle {np.bincount(ost)}", flush=True)
+    # near-tangent loopers may flip between NO_CROSSING and a crossing; they must be rare
+    same = gst == ost
+    assert same.mean() >= 0.9995 or (~same).sum() <= 1
+    ok = same & (gst == 0)
+    assert np.array_equal(gnh[ok], onh[ok])
+    w1 = check_params(gs[ok], os_[ok], "fit state")
+    w2 = check_chi2(gchi[ok], ochi[ok], "fit chi2")
+    w3 = check_cov(gc[ok], oc[ok], "fit cov")
+    print(f"[fit parity] worst rel: state {w1:.2e} chi2 {w2:.2e} cov {w3:.2e}", flush=True)
+
+
+def test_fit_edge_cases(ctx, orc):
+    import torch
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    fp = S.make_fit_problem(70, det, 7, p_miss=0.05, min_hits=6)
+    fp.hit_idx[:, 3] = -1  # a track without hits: output = input, nhits 0
+    fp.state0[5, 0] = np.nan  # non-finite input
+    fp.state0[9, 3:5] = [0.02, 0.0]  # pT = 20 MeV: diameter 3.5 cm never reaches r = 4 cm
+    gs, gc, gchi, gnh, gst = _fit_gpu(ctx, fp)
+    os_, oc, ochi, onh, ost = oracle_fit_on_f32(orc, det32, fp)
+    assert gst[3] == 0 and gnh[3] == 0 and np.allclose(gs[3], rounded(fp.state0[3]))
+    assert gst[5] == 4 and ost[5] == 4  # NONFINITE
+    assert gst[9] == ost[9] == 1
+    ok = (gst == 0) & (ost == 0)
+    check_params(gs[ok], os_[ok])
+    # n = 0 is a no-op
+    z = torch.empty(6, 0, device="cuda")
+    ctx.kf_fit(z, torch.empty(21, 0, device="cuda"), torch.empty(0, dtype=torch.int8, device="cuda"),
+               torch.empty(17, 0, dtype=torch.int32, device="cuda"), torch.empty(3, 1, device="cuda"),
+               torch.empty(6, 1, device="cuda"), z, torch.empty(21, 0, device="cuda"), torch.empty(0, device="cuda"),
+               torch.empty(0, dtype=torch.int32, device="cuda"), torch.empty(0, dtype=torch.int32, device="cuda"))
+
+
+def test_fit_rejects_bad_arguments(ctx):
+    import torch
+    from paper_1705_02876_amd import kfmi
+    det = S.detector_full()
+    ctx.kf_set_geometry(det.as_float32())
+    st = torch.zeros(6, 10, device="cuda")
+    with pytest.raises(kfmi.KfError):
+        ctx.kf_fit(st, torch.zeros(21, 10, device="cuda"), torch.zeros(10, dtype=torch.int8, device="cuda"),
+                   torch.zeros(17, 5, dtype=torch.int32, device="cuda"),  # ld_idx < n
+                   torch.zeros(3, 10, device="cuda"), torch.zeros(6, 10, device="cuda"), st,
+                   torch.zeros(21, 10, device="cuda"), torch.zeros(10, device="cuda"),
+                   torch.zeros(10, dtype=torch.int32, device="cuda"), torch.zeros(10, dtype=torch.int32, device="cuda"))
+    bad = kfmi.geometry_struct(det)
+    bad.r[3] = bad.r[2]
+    with pytest.raises(kfmi.KfError):
+        ctx.kf_set_geometry(bad)
+    ctx.kf_set_geometry(det.as_float32())
+
+
+def test_propagate_parity(ctx, orc):
+    import torch
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    g = orc.geometry(det32)
+    n = 5003
+    fp = S.make_fit_problem(n, det, 55)
+    # start on layer 3 (truth there) with the workload's prior widths, go to layer 4 with layer-3 material
+    tp = fp.extra["true_pos"][3]
+    tm = fp.extra["true_mom"][3]
+    ok = np.isfinite(tp[:, 0])
+    s0 = np.concatenate([tp, tm], axis=1)[ok]
+    C0 = fp.cov0[ok]
+    q = fp.q[ok]
+    m = s0.shape[0]
+    st_d = to_dev(soa_state(s0))
+    cv_d = to_dev(soa_cov(C0))
+    q_d = to_dev(q.astype(np.int8))
+    stat = torch.empty(m, dtype=torch.int32, device="cuda")
+    ctx.kf_propagate_to_r(st_d, cv_d, q_d, stat, r_scalar=float(det32.radii[4]), z_half=float(det32.z_half),
+                          material_layer=3)
+    torch.cuda.synchronize()
+    gs, gc = from_soa_state(st_d), from_soa_cov(cv_d)
+    gst = stat.cpu().numpy()
+    os_, oc, ost = orc.propagate(g, rounded(s0), rounded(S.unpack6(S.pack6(C0))), q, r_scalar=det32.radii[4],
+                                 z_half=det32.z_half, material_layer=3)
+    assert np.array_equal(gst, ost)
+    good = gst == 0
+    w = check_params(gs[good], os_[good], "propagate state")
+    wc = check_cov(gc[good], oc[good], "propagate cov")
+    print(f"[propagate parity] n={m} worst state {w:.2e} cov {wc:.2e}", flush=True)
+    # exits: steep tracks leave |z| < z_half; soft ones never reach r = 100
+    s1 = np.array([[0, 0, 0, 5.0, 0.0, 20.0], [0, 0, 0, 0.3, 0.0, 0.1], [0, 0, 0, 1.0, 1.0, 0.2]])
+    st_d = to_dev(soa_state(s1))
+    cv_d = to_dev(soa_cov(np.repeat(np.eye(6)[None] * 1e-4, 3, 0)))
+    stat = torch.empty(3, dtype=torch.int32, device="cuda")
+    ctx.kf_propagate_to_r(st_d, cv_d, to_dev(np.array([1, 1, -1], np.int8)), stat,
+                          r_target=to_dev(np.array([20.0, 100.0, 10.0], np.float32)), z_half=50.0)
+    assert list(stat.cpu().numpy()) == [2, 1, 0]
+
+
+def test_update_parity(ctx, orc):
+    import torch
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    g = orc.geometry(det32)
+    fp = S.make_fit_problem(3001, det, 56)
+    s1, C1, st = orc.propagate(g, rounded(fp.state0), rounded(S.unpack6(S.pack6(fp.cov0))), fp.q,
+                               r_scalar=det32.radii[0])
+    assert (st == 0).all()
+    hits = fp.hit_pos[fp.hit_idx[0]]
+    hc = fp.hit_cov[fp.hit_idx[0]]
+    s1r, C1r = rounded(s1), rounded(C1)
+    for chi2_only in (True, False):
+        st_d = to_dev(soa_state(s1r))
+        cv_d = to_dev(soa_cov(C1r))
+        chi2 = torch.empty(s1.shape[0], device="cuda")
+        stat = torch.empty(s1.shape[0], dtype=torch.int32, device="cuda")
+        ctx.kf_update(st_d, cv_d, to_dev(np.ascontiguousarray(rounded(hits).T.astype(np.float32))),
+                      to_dev(np.ascontiguousarray(hc.T.astype(np.float32))), chi2, stat, chi2_only=chi2_only)
+        torch.cuda.synchronize()
+        os_, oc, ochi, ost = orc.update(s1r, C1r, rounded(hits), S.unpack3(rounded(hc)), chi2_only=chi2_only)
+        assert np.array_equal(stat.cpu().numpy(), ost)
+        check_chi2(chi2.cpu().numpy().astype(np.float64), ochi, "update chi2")
+        check_params(from_soa_state(st_d), os_, "update state")
+        check_cov(from_soa_cov(cv_d), oc, "update cov")
+        if chi2_only:
+            assert np.array_equal(from_soa_state(st_d), s1r.astype(np.float32).astype(np.float64))
+
+
+def test_fit_full_size_sampled(ctx, orc):
+    """2M tracks, 17 layers (the bench workload and launch); 3000 sampled tracks against the oracle."""
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    from paper_1705_02876_amd import workloads
+    fp = workloads.fit_workload(det, 2_000_000)
+    gs, gc, gchi, gnh, gst = _fit_gpu(ctx, fp)
+    rng = np.random.Generator(np.random.PCG64(9))
+    idx = np.sort(rng.choice(fp.state0.shape[0], 3000, replace=False))
+    sub = S.FitProblem(det, fp.q[idx], fp.state0[idx], fp.cov0[idx], fp.hit_idx[:, idx], fp.hit_pos, fp.hit_cov,
+                       fp.truth_state0[idx], fp.truth_last[idx], fp.last_layer[idx])
+    os_, oc, ochi, onh, ost = oracle_fit_on_f32(orc, det32, sub)
+    same = gst[idx] == ost
+    assert (~same).sum() <= 1
+    ok = same & (ost == 0)
+    assert np.array_equal(gnh[idx][ok], onh[ok])
+    check_params(gs[idx][ok], os_[ok], "full-size fit state")
+    check_chi2(gchi[idx][ok], ochi[ok], "full-size fit chi2")
+    check_cov(gc[idx][ok], oc[ok], "full-size fit cov")
+    # properties over all 2M: finite outputs, nhits = assigned hits for converged tracks
+    allok = gst == 0
+    assert allok.mean() > 0.999
+    assert np.isfinite(gs[allok]).all() and np.isfinite(gchi[allok]).all()
+    assert np.array_equal(gnh[allok], (fp.hit_idx >= 0).sum(axis=0)[allok])
+
+
+def test_residual_emission(ctx, orc):
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    fp = S.make_fit_problem(500, det, 58, p_miss=0.05, min_hits=6)
+    (gs, gc, gchi, gnh, gst), res = _fit_gpu(ctx, fp, residuals=True)
+    L = det.n_layers
+    rows = res.reshape(10, 500, L - 1)
+    has = fp.hit_idx[1:].T >= 0  # (n, L-1)
+    last = fp.last_layer
+    finite = np.isfinite(rows[0])
+    # a record for every hit on layer >= 1 up to the last one, NaN elsewhere
+    assert np.array_equal(finite, has)
+    # targets: tangential offsets are O(prediction sigma), z offsets too
+    assert np.nanstd(rows[8]) < 0.5 and np.nanstd(rows[9]) < 2.0
