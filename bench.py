@@ -6,7 +6,7 @@ A step is one pass of the hot path over one batch of synthetic input that is
 already resident in HBM: the fit of the full fit workload (2 000 000 tracks,
 17 layers r = 4..100 cm, 0.02 X0 per layer with energy loss, 5% missing hits,
 6-17 hits per track), then hit binning and combinatorial building of the
-batched workload when the build is available.  W untimed warm-up steps, then
+batched workload (64 events, log-uniform 1k-50k tracks, 20% noise hits).  W untimed warm-up steps, then
 exactly K timed steps bracketed by device synchronisation; HIP events on the
 stream the kernels run on give per-kernel durations for the roofline.
 Prints one JSON line.
@@ -50,7 +50,7 @@ def fit_flops(fp):
     return FLOP_PER_LAYER * int(layers) + FLOP_PER_HIT * int(hits) + FLOP_PER_MATERIAL * int(mats)
 
 
-def cpu_baseline_fit(fp, det32, max_tracks=300_000):
+def cpu_baseline_fit(fp, det32, max_tracks=2_000_000):
     """Oracle fit (FP64 C, as it stands) on a bounded sample of the same workload, all host cores."""
     import oracle as orc
     from concurrent.futures import ThreadPoolExecutor
@@ -79,6 +79,68 @@ def cpu_baseline_fit(fp, det32, max_tracks=300_000):
                       f"{dt:.2f} s wall"}
 
 
+# Algorithmic work of the build, counted from the kernel source and the device counters:
+#   per candidate-layer step: material 70 + crossing/Jacobian/transport 615 + window ~40 FLOP
+#   per box-tested hit: 8 FLOP; per chi2 evaluation: 70 FLOP; per survivor update with a hit: 322 FLOP
+BUILD_FLOP_STEP = 725
+BUILD_FLOP_BOX = 8
+BUILD_FLOP_CHI2 = 70
+BUILD_FLOP_UPDATE = FLOP_PER_HIT
+
+
+def build_flops(cnt):
+    box, chi2, comp, steps, upd = [int(x) for x in cnt]
+    return BUILD_FLOP_STEP * steps + BUILD_FLOP_BOX * box + BUILD_FLOP_CHI2 * chi2 + BUILD_FLOP_UPDATE * upd
+
+
+def build_bytes(prob, N, L):
+    """Seeds in (27 f32 + charge + 3 hit indices), every binned hit record read once (48 B), hit
+    positions/covariances read once by the binning (36 B) and written as records (48 B) plus bins/perm,
+    outputs (candidate hits N*L int32, chi2/nhits/status 3N, best state+cov 27 f32, n_cands)."""
+    S = prob.seed_state.shape[0]
+    H = prob.hit_pos.shape[0]
+    return S * (108 + 1 + 12) + H * 48 + S * (4 * N * L + 12 * N + 108 + 4)
+
+
+def bin_bytes(prob, L, n_bins=1024):
+    H = prob.hit_pos.shape[0]
+    return H * (36 + 48 + 4 + 4 + 4) + prob.n_events * L * (n_bins + 1) * 4
+
+
+def cpu_baseline_build(prob, det32, max_seeds=300_000, N=6):
+    """Oracle build (FP64 C, binned mode, as it stands) on the first events of the batched workload."""
+    import oracle as orc
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1705_02876_amd import synth as S
+    cum = np.asarray(prob.seed_offsets)
+    ne = int(np.searchsorted(cum, max_seeds, side="right") - 1)
+    ne = max(ne, 1)
+    L = det32.n_layers
+    hend = int(prob.layer_hit_offsets[ne * L])
+    sub = S.BuildProblem(det=prob.det, n_events=ne, layer_hit_offsets=prob.layer_hit_offsets[: ne * L + 1],
+                         hit_pos=prob.hit_pos[:hend], hit_cov=prob.hit_cov[:hend], hit_track=prob.hit_track[:hend],
+                         seed_offsets=prob.seed_offsets[: ne + 1], seed_state=prob.seed_state[: cum[ne]],
+                         seed_cov=prob.seed_cov[: cum[ne]], seed_q=prob.seed_q[: cum[ne]],
+                         seed_hits=prob.seed_hits[: cum[ne]], seed_track=prob.seed_track[: cum[ne]],
+                         track_nhits=prob.track_nhits[:ne])
+    nseeds = int(cum[ne])
+    cores = min(os.cpu_count() or 1, 64)
+    g = orc.geometry(det32)
+    r32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    hp, hc = r32(sub.hit_pos), S.unpack3(r32(sub.hit_cov))
+    ss, sc = r32(sub.seed_state), S.unpack6(r32(S.pack6(sub.seed_cov)))
+    chunks = np.array_split(np.arange(nseeds), cores)
+    orc.lib()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(lambda ix: orc.build(g, sub, max_cands=N, mode=1, seeds=ix, hit_pos=hp, hit_cov_full=hc,
+                                         seed_state=ss, seed_cov=sc), chunks))
+    dt = time.perf_counter() - t0
+    return {"value": nseeds / dt, "unit": "seeds/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {ne} events ({nseeds} seeds) of the batched build workload, FP64 oracle binned "
+                      f"build N={N}, {cores} host threads (each bins the sample's hits), {dt:.2f} s wall"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +148,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tracks", type=int, default=2_000_000)
+    ap.add_argument("--events", type=int, default=64)
+    ap.add_argument("--build-mode", choices=["tiled", "persistent"], default="persistent")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -96,56 +160,101 @@ def main():
     det = S.detector_full()
     det32 = det.as_float32()
     fp = W.fit_workload(det, args.tracks)
-    print(f"[bench] generated fit workload in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    print(f"[bench] fit workload generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    t0 = time.time()
+    bp = W.batched_workload(args.events, det)
+    print(f"[bench] build workload generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
     import torch
-    from paper_1705_02876_amd import kfmi
+    from paper_1705_02876_amd import kfmi, kfmi_build as KB
     ctx = kfmi.Context(0)
     ctx.kf_set_geometry(det32)
     n = fp.state0.shape[0]
     L = det.n_layers
     dev = "cuda"
-    st_in = torch.from_numpy(np.ascontiguousarray(fp.state0.T.astype(np.float32))).to(dev)
-    cv_in = torch.from_numpy(np.ascontiguousarray(S.pack6(fp.cov0).T.astype(np.float32))).to(dev)
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).to(dev)
+    st_in, cv_in = f32(fp.state0.T), f32(S.pack6(fp.cov0).T)
     q = torch.from_numpy(fp.q.astype(np.int8)).to(dev)
     hidx = torch.from_numpy(np.ascontiguousarray(fp.hit_idx)).to(dev)
-    hpos = torch.from_numpy(np.ascontiguousarray(fp.hit_pos.T.astype(np.float32))).to(dev)
-    hcov = torch.from_numpy(np.ascontiguousarray(fp.hit_cov.T.astype(np.float32))).to(dev)
-    st_out = torch.empty_like(st_in)
-    cv_out = torch.empty_like(cv_in)
+    hpos, hcov = f32(fp.hit_pos.T), f32(fp.hit_cov.T)
+    st_out, cv_out = torch.empty_like(st_in), torch.empty_like(cv_in)
     chi2 = torch.empty(n, dtype=torch.float32, device=dev)
     nh = torch.empty(n, dtype=torch.int32, device=dev)
     stat = torch.empty(n, dtype=torch.int32, device=dev)
+    # build inputs and outputs, all resident
+    seeds, hits = KB.upload_problem(bp)
+    N = 6
+    mode = KB.BUILD_PERSISTENT if args.build_mode == "persistent" else KB.BUILD_TILED
+    cfg = KB.make_cfg(max_cands=N, mode=mode)
+    bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events)
+    bws_bytes = kfmi.load_library().kf_bin_hits_workspace_size(hits["pos"].shape[1])
+    bws = torch.empty(max(bws_bytes, 4), dtype=torch.uint8, device=dev)
+    bout = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events)
+    cnt = torch.zeros(5, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
 
     def fit_step():
         ctx.kf_fit(st_in, cv_in, q, hidx, hpos, hcov, st_out, cv_out, chi2, nh, stat)
 
+    def bin_step():
+        KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events, out=bins, workspace=bws)
+
+    def build_step(counters=None):
+        KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=bout, counters=counters)
+
     for _ in range(args.warmup):
         fit_step()
+        bin_step()
+        build_step()
+    build_step(cnt)  # one extra call for the work counters (outside the timed region)
     torch.cuda.synchronize()
+    counters = cnt.cpu().numpy()
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    E = lambda: torch.cuda.Event(enable_timing=True)
+    ev = [[E() for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record(stream)
         fit_step()
         ev[k][1].record(stream)
+        bin_step()
+        ev[k][2].record(stream)
+        build_step()
+        ev[k][3].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    fit_ms = [a.elapsed_time(b) for a, b in ev]
-    fit_avg_ms = float(np.mean(fit_ms))
+    fit_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    bin_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    build_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
     ms_per_step = wall * 1e3 / args.steps
-    tracks_per_s = n * args.steps / wall
+    tracks_per_s = n / (fit_ms * 1e-3)
+    n_seeds = bp.seed_state.shape[0]
+    seeds_per_s = n_seeds / ((bin_ms + build_ms) * 1e-3)
 
     n_hits = int((fp.hit_idx >= 0).sum())
-    bytes_launch = fit_bytes(n, L, n_hits)
-    flops_launch = fit_flops(fp)
-    achieved_tflops = flops_launch / (fit_avg_ms * 1e-3) / 1e12
-    achieved_gbs = bytes_launch / (fit_avg_ms * 1e-3) / 1e9
-    nbad = int((stat != 0).sum().item())
-
+    kern = {}
+    fb = fit_bytes(n, L, n_hits)
+    ff = fit_flops(fp)
+    kern["fit_kernel"] = dict(avg_ms=fit_ms, flop=ff, bytes=fb)
+    kern["bin_kernel"] = dict(avg_ms=bin_ms, flop=0, bytes=bin_bytes(bp, L))
+    kern["build_persistent_kernel" if mode else "build_tiled_kernel"] = dict(
+        avg_ms=build_ms, flop=build_flops(counters), bytes=build_bytes(bp, N, L))
+    for k, v in kern.items():
+        sec = v["avg_ms"] * 1e-3
+        v["tflops"] = v["flop"] / sec / 1e12
+        v["gbs"] = v["bytes"] / sec / 1e9
+        v["alu_frac"] = v["tflops"] / FP32_VECTOR_PEAK_TFLOPS
+        v["hbm_frac"] = v["gbs"] / HBM_PEAK_GBS
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"])
+    d = kern[dom]
+    if d["alu_frac"] >= d["hbm_frac"]:
+        roof = {"bound": "alu", "achieved": d["tflops"], "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": d["alu_frac"], "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["hbm_frac"], "traffic": None}
+    roof["kernel"] = dom
     out = {
         "metric": METRIC,
         "value": tracks_per_s,
@@ -157,20 +266,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32 (Kalman update f64)",
         "data": "synthetic",
         "config": {"workload": "full fit: 2M tracks, 17 barrel layers r=4..100 cm, 0.02 X0/layer + energy loss, "
-                               "5% missing hits (6-17 hits), pT U[0.5,10] GeV, |eta|<1, Bz=3.8 T",
-                   "tracks": n, "layers": L, "hits": n_hits},
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "fit_kernel", "avg_ms": fit_avg_ms, "flop_per_launch": flops_launch,
-                     "hbm_gbs": achieved_gbs, "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
-                     "bytes_per_launch": bytes_launch},
-        "fit_status_nonzero": nbad,
+                               "5% missing hits (6-17 hits), pT U[0.5,10] GeV, |eta|<1, Bz=3.8 T; "
+                               "then batched build: 64 events log-uniform [1k,50k] tracks + 20% noise hits, "
+                               "64x16 bins, N=6, chi2<30",
+                   "tracks": n, "layers": L, "fit_hits": n_hits, "events": bp.n_events, "seeds": n_seeds,
+                   "build_hits": int(bp.hit_pos.shape[0]), "build_mode": args.build_mode},
+        "seeds_built_per_s": seeds_per_s,
+        "fit_ms": fit_ms, "bin_ms": bin_ms, "build_ms": build_ms,
+        "roofline": roof,
+        "kernels": kern,
+        "build_counters": {"box_tests": int(counters[0]), "chi2_evals": int(counters[1]),
+                           "compatible": int(counters[2]), "cand_layer_steps": int(counters[3]),
+                           "updates": int(counters[4])},
+        "fit_status_nonzero": int((stat != 0).sum().item()),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_fit(fp, det32)
+        out["cpu_baseline_build"] = cpu_baseline_build(bp, det32)
     print(json.dumps(out), flush=True)
 
 

@@ -148,6 +148,128 @@ typedef struct {
 } kf_fit_args;
 int32_t kf_fit(kf_ctx* ctx, const kf_fit_args* args);
 
+
+/* ------------------------------------------------------------------------
+ * Hit binning (Sec. 3: hits of each layer are placed into directionally
+ * projective bins that give a fast look-up of the hits compatible with a
+ * track's estimate; Sec. 4.3: on the GPU this reorganisation runs on the
+ * device).  For every (event e, layer l) the hits [layer_offsets[e*L+l],
+ * layer_offsets[e*L+l+1]) are binned by
+ *   i_phi = floor((atan2(y, x) + pi) n_phi / (2 pi)),
+ *   i_eta = floor((asinh(z / r_l) + eta_l) n_eta / (2 eta_l)),
+ *   eta_l = asinh(z_half_l / r_l),          both clamped to their range,
+ * evaluated in double precision on the float32 coordinates; bin id =
+ * i_eta * n_phi + i_phi.  The sort is stable: inside a bin hits keep their
+ * original order.
+ * Inputs (device): layer_offsets [n_events * n_layers + 1] int64 (ascending,
+ * last entry <= ldh), hit_pos [3][ldh], hit_cov [6][ldh].
+ * Outputs (device):
+ *   bin_offsets [n_events * n_layers][n_phi * n_eta + 1] int32 -- absolute
+ *               slot indices, bin b of (e, l) holds slots [o[b], o[b+1]);
+ *   perm [ldh] int32 -- original hit index of each slot;
+ *   binned [ldh][KF_BINNED_FLOATS] float32 -- the hit record of each slot:
+ *               x, y, z, local index (int32 bits, index within its (e, l)),
+ *               then the packed covariance (6), then 2 zero pads (48 bytes);
+ *   layer_vmax [n_events * n_layers][2] float32 -- largest x-y eigenvalue
+ *               and largest zz variance of the layer's hit covariances.
+ * Workspace: kf_bin_hits_workspace_size(ldh) bytes of device memory owned
+ * by the caller (per-hit bin ids). */
+#define KF_BINNED_FLOATS 12
+typedef struct {
+  int64_t n_events;
+  const int64_t* layer_offsets;
+  const float* hit_pos;
+  const float* hit_cov;
+  int64_t ldh;
+  int32_t n_phi, n_eta;
+  int32_t* bin_offsets;
+  int32_t* perm;
+  float* binned;
+  float* layer_vmax;
+  void* workspace;
+  size_t workspace_bytes;
+  void* stream;
+} kf_bin_args;
+size_t kf_bin_hits_workspace_size(int64_t ldh);
+int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* args);
+
+/* ------------------------------------------------------------------------
+ * Combinatorial track building (Sec. 3 "best hit" and combinatorial KF,
+ * Sec. 3.1 clone engine, Sec. 4.3 ranking by number of hits then chi2).
+ * Every seed starts as one candidate with nhits = 3 and chi2 = 0 at the
+ * layer of its third hit.  For each layer l = first_layer .. n_layers-1 every
+ * live candidate gets the material of layer l-1, is propagated to layer l
+ * (|z| <= z_half), and emits one child per hit of the same event and layer
+ * with chi2 increment < chi2_cut (found through the bins overlapping the
+ * box |r sin(dphi)| <= sqrt(cut R_tt), |dz| <= sqrt(cut R_zz), which bounds
+ * the chi2 ellipsoid) plus one hole child without a hit; a candidate that
+ * cannot be propagated (status bits) is carried unchanged as its only child.
+ * All children of a seed are ranked by (more hits, smaller chi2, parent
+ * rank, hit index, hole last) and the best max_cands survive; only the
+ * survivors are updated (clone engine).  max_cands = 1 is the best-hit
+ * search.
+ * Seeds (device): seed_offsets [n_events+1] int64 (seeds of event e are
+ * [o[e], o[e+1])), seed_state [6][ld_seed], seed_cov [21][ld_seed],
+ * seed_charge [n_seeds] int8, seed_hits [3][ld_seed] int32 (global hit
+ * indices of layers 0..2, copied to the output hit lists).
+ * Hits: layer_offsets as for kf_bin_hits and its outputs bin_offsets,
+ * binned, layer_vmax with the same n_phi, n_eta.
+ * Outputs (device), N = max_cands, S = n_seeds:
+ *   n_cands [S] int32; cand_hits [n_layers][S][N] int32 (global hit index,
+ *   -1 = no hit; slots k >= n_cands[s] are -1); cand_chi2 [S][N] float32;
+ *   cand_nhits [S][N] int32; cand_status [S][N] int32; best_state [6][ld_seed]
+ *   and best_cov [21][ld_seed] of the rank-0 candidate (nullable);
+ *   counters [KF_BUILD_COUNTERS] uint64 (nullable, accumulated): hits
+ *   box-tested, chi2 evaluations, compatible hits, candidate-layer steps,
+ *   survivor updates with a hit.
+ * Modes: KF_BUILD_TILED (default) runs every layer of a tile of seeds inside
+ * one launch; KF_BUILD_PERSISTENT launches one grid sized to the device
+ * whose waves pull tiles from a device work queue (needs workspace).
+ * window_mode KF_WINDOW_LEARNED uses the network given by kf_build_set_mlp
+ * (see below) and falls back to the plain window for a candidate when no hit
+ * passes in the learned one. */
+#define KF_BUILD_COUNTERS 5
+#define KF_BUILD_TILED 0
+#define KF_BUILD_PERSISTENT 1
+#define KF_WINDOW_PLAIN 0
+#define KF_WINDOW_LEARNED 1
+typedef struct {
+  int32_t max_cands;   /* 1..8 */
+  float chi2_cut;      /* > 0 */
+  int32_t n_phi, n_eta;
+  float window_margin; /* relative margin on the window half widths, >= 0 */
+  int32_t mode;        /* KF_BUILD_TILED or KF_BUILD_PERSISTENT */
+  int32_t window_mode; /* KF_WINDOW_PLAIN or KF_WINDOW_LEARNED */
+  int32_t waves_per_block; /* 0 = library choice */
+  int32_t blocks_per_cu;   /* persistent mode occupancy, 0 = library choice */
+} kf_build_cfg;
+typedef struct {
+  int64_t n_events, n_seeds, ld_seed;
+  int32_t first_layer;
+  const int64_t* seed_offsets;
+  const float* seed_state;
+  const float* seed_cov;
+  const int8_t* seed_charge;
+  const int32_t* seed_hits;
+  const int64_t* layer_offsets;
+  const int32_t* bin_offsets;
+  const float* binned;
+  const float* layer_vmax;
+  int32_t* n_cands;
+  int32_t* cand_hits;
+  float* cand_chi2;
+  int32_t* cand_nhits;
+  int32_t* cand_status;
+  float* best_state;
+  float* best_cov;
+  uint64_t* counters;
+  void* workspace;
+  size_t workspace_bytes;
+  void* stream;
+} kf_build_args;
+size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_seeds);
+int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* args);
+
 #ifdef __cplusplus
 }
 #endif

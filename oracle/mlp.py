@@ -1,0 +1,99 @@
+"""FP64 reference of the learned search-window network (test infrastructure only).
+
+Network 8 -> 64 -> 64 -> 2 with ReLU hidden layers:
+    h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3.
+The two outputs are log scales (log s_t, log s_z) of the tangential and z
+residuals of a track's own hit around the propagated prediction.  Training
+minimises the Gaussian negative log-likelihood per record
+    l = sum_k [ r_k^2 exp(-2 o_k) / 2 + o_k ],
+averaged over the batch; the optimiser is Adam (Kingma & Ba, 2015) with
+bias-corrected moments.  Parameters are kept in a dict of float64 arrays.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SIZES = (8, 64, 64, 2)
+NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def n_params():
+    return sum(SIZES[i + 1] * SIZES[i] + SIZES[i + 1] for i in range(3))
+
+
+def init(seed):
+    """He-uniform weights, zero biases (seeded)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = {}
+    for i in range(3):
+        fan_in, fan_out = SIZES[i], SIZES[i + 1]
+        lim = np.sqrt(6.0 / fan_in)
+        p[f"W{i + 1}"] = rng.uniform(-lim, lim, (fan_out, fan_in))
+        p[f"b{i + 1}"] = np.zeros(fan_out)
+    return p
+
+
+def flatten(p):
+    """Parameters as one vector in the order W1, b1, W2, b2, W3, b3 (row-major)."""
+    return np.concatenate([p[k].ravel() for k in NAMES])
+
+
+def unflatten(v):
+    p = {}
+    off = 0
+    for i in range(3):
+        fo, fi = SIZES[i + 1], SIZES[i]
+        p[f"W{i + 1}"] = v[off:off + fo * fi].reshape(fo, fi)
+        off += fo * fi
+        p[f"b{i + 1}"] = v[off:off + fo].copy()
+        off += fo
+    return p
+
+
+def forward(p, X):
+    """X (B, 8) -> outputs (B, 2) and the hidden activations."""
+    a1 = X @ p["W1"].T + p["b1"]
+    h1 = np.maximum(a1, 0.0)
+    a2 = h1 @ p["W2"].T + p["b2"]
+    h2 = np.maximum(a2, 0.0)
+    o = h2 @ p["W3"].T + p["b3"]
+    return o, (a1, h1, a2, h2)
+
+
+def loss(p, X, T):
+    o, _ = forward(p, X)
+    return float(np.mean(np.sum(0.5 * T * T * np.exp(-2.0 * o) + o, axis=1)))
+
+
+def grad(p, X, T):
+    """Mean loss and its gradient (dict like p), by the chain rule."""
+    B = X.shape[0]
+    o, (a1, h1, a2, h2) = forward(p, X)
+    L = float(np.mean(np.sum(0.5 * T * T * np.exp(-2.0 * o) + o, axis=1)))
+    do = (1.0 - T * T * np.exp(-2.0 * o)) / B
+    g = {"W3": do.T @ h2, "b3": do.sum(axis=0)}
+    dh2 = do @ p["W3"]
+    da2 = dh2 * (a2 > 0)
+    g["W2"] = da2.T @ h1
+    g["b2"] = da2.sum(axis=0)
+    dh1 = da2 @ p["W2"]
+    da1 = dh1 * (a1 > 0)
+    g["W1"] = da1.T @ X
+    g["b1"] = da1.sum(axis=0)
+    return L, g
+
+
+def adam_step(p, g, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update in place; state = dict(m, v, t) (created if empty)."""
+    if not state:
+        state.update(m={k: np.zeros_like(v) for k, v in p.items()}, v={k: np.zeros_like(v) for k, v in p.items()},
+                     t=0)
+    state["t"] += 1
+    t = state["t"]
+    for k in p:
+        state["m"][k] = beta1 * state["m"][k] + (1 - beta1) * g[k]
+        state["v"][k] = beta2 * state["v"][k] + (1 - beta2) * g[k] * g[k]
+        mh = state["m"][k] / (1 - beta1 ** t)
+        vh = state["v"][k] / (1 - beta2 ** t)
+        p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
+    return p

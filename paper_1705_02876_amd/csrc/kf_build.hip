@@ -1,0 +1,657 @@
+// kf_build.hip -- hit binning and combinatorial track building on gfx950.
+//
+// Binning: one 1024-thread workgroup per (event, layer).  Each of its 16
+// waves owns a contiguous slice of the layer's hits: it computes their bins
+// (double precision, the decision the oracle takes too), counts them in its
+// own LDS histogram, and after a block-wide prefix over (bin, wave) scatters
+// its slice in order, ranking equal bins inside a 64-hit chunk with ballots.
+// The result is a stable counting sort with no global atomics.
+//
+// Building: one wave holds 64/G seeds and G >= max_cands lanes per seed, one
+// lane per candidate slot.  All layers of a tile run inside the kernel with
+// the candidates in registers: propagate, window, scan the window's bins
+// (box pre-test, then chi2), keep a per-candidate sorted list of its best
+// max_cands children, merge the lists of a seed with G-lane reductions of a
+// 64-bit rank key, and update only the survivors (clone engine).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "kf_internal.hpp"
+
+using namespace kfd;
+
+namespace {
+
+constexpr int kBinWaves = 16;
+constexpr int kBinThreads = kBinWaves * 64;
+constexpr int kMaxBins = 2048;
+constexpr uint32_t kHole = 0xFFFFFFu;
+
+__device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, double zh, int n_phi, int n_eta) {
+#pragma clang fp contract(off)
+  const double phi = atan2(static_cast<double>(yf), static_cast<double>(xf));
+  int ip = static_cast<int>(floor((phi + M_PI) * static_cast<double>(n_phi) / (2.0 * M_PI)));
+  ip = ip < 0 ? 0 : (ip > n_phi - 1 ? n_phi - 1 : ip);
+  const double eta = asinh(static_cast<double>(zf) / R);
+  const double emax = asinh(zh / R);
+  int ie = static_cast<int>(floor((eta + emax) * static_cast<double>(n_eta) / (2.0 * emax)));
+  ie = ie < 0 ? 0 : (ie > n_eta - 1 ? n_eta - 1 : ie);
+  return ie * n_phi + ip;
+}
+
+__global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64_t* __restrict__ layer_offsets,
+                                                          const float* __restrict__ hit_pos,
+                                                          const float* __restrict__ hit_cov, int64_t ldh,
+                                                          int32_t n_phi, int32_t n_eta, Geom g,
+                                                          int32_t* __restrict__ bins, int32_t* __restrict__ bin_offsets,
+                                                          int32_t* __restrict__ perm, float* __restrict__ binned,
+                                                          float* __restrict__ layer_vmax) {
+  __shared__ int32_t cnt[kBinWaves][kMaxBins];
+  __shared__ int32_t tot[kMaxBins];
+  __shared__ int32_t wsum[kBinWaves];
+  __shared__ uint32_t vmax_bits[2];
+  const int el = blockIdx.x;
+  const int l = el % L;
+  const int nb = n_phi * n_eta;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int64_t lo = layer_offsets[el], hi = layer_offsets[el + 1];
+  const int64_t nh = hi - lo;
+  for (int i = tid; i < kBinWaves * nb; i += kBinThreads) cnt[i / nb][i % nb] = 0;
+  if (tid < 2) vmax_bits[tid] = 0u;
+  __syncthreads();
+  // this wave's contiguous slice
+  const int64_t per = (nh + kBinWaves - 1) / kBinWaves;
+  const int64_t a = lo + per * wave;
+  const int64_t b = (a + per < hi) ? a + per : hi;
+  const double R = static_cast<double>(g.r[l]);
+  const double zh = static_cast<double>(g.z_half[l]);
+  float my_vxy = 0.f, my_vz = 0.f;
+  for (int64_t h = a + lane; h < b; h += 64) {
+    const int bin = hit_bin(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h], R, zh, n_phi, n_eta);
+    bins[h] = bin;
+    atomicAdd(&cnt[wave][bin], 1);
+    const float vxx = hit_cov[h], vyx = hit_cov[ldh + h], vyy = hit_cov[2 * ldh + h], vzz = hit_cov[5 * ldh + h];
+    const float d = 0.5f * (vxx - vyy);
+    my_vxy = fmaxf(my_vxy, 0.5f * (vxx + vyy) + sqrtf(d * d + vyx * vyx));
+    my_vz = fmaxf(my_vz, vzz);
+  }
+  atomicMax(&vmax_bits[0], __float_as_uint(my_vxy));  // non-negative floats order like their bits
+  atomicMax(&vmax_bits[1], __float_as_uint(my_vz));
+  __syncthreads();
+  // per bin: exclusive prefix over waves, bin totals
+  for (int bin = tid; bin < nb; bin += kBinThreads) {
+    int run = 0;
+#pragma unroll
+    for (int w = 0; w < kBinWaves; ++w) {
+      const int c = cnt[w][bin];
+      cnt[w][bin] = run;
+      run += c;
+    }
+    tot[bin] = run;
+  }
+  __syncthreads();
+  // exclusive scan of the bin totals (each wave scans a contiguous block of bins)
+  const int per_w = (nb + kBinWaves - 1) / kBinWaves;
+  const int b0 = wave * per_w;
+  const int b1 = (b0 + per_w < nb) ? b0 + per_w : nb;
+  int wrun = 0;
+  for (int base = b0; base < b1; base += 64) {
+    const int bin = base + lane;
+    int v = (bin < b1) ? tot[bin] : 0;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off);
+      if (lane >= off) x += y;
+    }
+    if (bin < b1) tot[bin] = wrun + x - v;  // exclusive within this wave's block
+    wrun += __shfl(x, 63);
+  }
+  if (lane == 0) wsum[wave] = wrun;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int w = 0; w < kBinWaves; ++w) {
+      const int c = wsum[w];
+      wsum[w] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  int32_t* bo = bin_offsets + static_cast<int64_t>(el) * (nb + 1);
+  for (int bin = tid; bin < nb; bin += kBinThreads) {
+    const int off = tot[bin] + wsum[bin / per_w];
+    tot[bin] = off;
+    bo[bin] = static_cast<int32_t>(lo + off);
+  }
+  if (tid == 0) {
+    bo[nb] = static_cast<int32_t>(hi);
+    layer_vmax[2 * el] = __uint_as_float(vmax_bits[0]);
+    layer_vmax[2 * el + 1] = __uint_as_float(vmax_bits[1]);
+  }
+  __syncthreads();
+  for (int bin = tid; bin < nb; bin += kBinThreads) {
+    const int base = tot[bin];
+#pragma unroll
+    for (int w = 0; w < kBinWaves; ++w) cnt[w][bin] += base;
+  }
+  __syncthreads();
+  // stable scatter of this wave's slice, 64 hits at a time, in index order
+  int nbits = 0;
+  while ((1 << nbits) < nb) ++nbits;
+  for (int64_t base = a; base < b; base += 64) {
+    const int64_t h = base + lane;
+    const bool valid = h < b;
+    const int bin = valid ? bins[h] : 0;
+    uint64_t m = __ballot(valid);
+    for (int bit = 0; bit < nbits; ++bit) {
+      const bool one = (bin >> bit) & 1;
+      const uint64_t bb = __ballot(one);
+      m &= one ? bb : ~bb;
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int rank = __popcll(m & lt);
+    int dest = 0;
+    if (valid) dest = cnt[wave][bin] + rank;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) cnt[wave][bin] += __popcll(m);
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+      const int64_t slot = lo + dest;
+      perm[slot] = static_cast<int32_t>(h);
+      float4* rec = reinterpret_cast<float4*>(binned + slot * KF_BINNED_FLOATS);
+      rec[0] = make_float4(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h],
+                           __int_as_float(static_cast<int32_t>(h - lo)));
+      rec[1] = make_float4(hit_cov[h], hit_cov[ldh + h], hit_cov[2 * ldh + h], hit_cov[3 * ldh + h]);
+      rec[2] = make_float4(hit_cov[4 * ldh + h], hit_cov[5 * ldh + h], 0.f, 0.f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// building
+// ---------------------------------------------------------------------------
+
+struct BuildP {
+  int64_t n_seeds, ld_seed;
+  int32_t n_events, first_layer, max_cands, n_phi, n_eta;
+  float chi2_cut, margin;
+  const int64_t* seed_offsets;
+  const float* seed_state;
+  const float* seed_cov;
+  const int8_t* seed_charge;
+  const int32_t* seed_hits;
+  const int64_t* layer_offsets;
+  const int32_t* bin_offsets;
+  const float* binned;
+  const float* layer_vmax;
+  int32_t* n_cands;
+  int32_t* cand_hits;
+  float* cand_chi2;
+  int32_t* cand_nhits;
+  int32_t* cand_status;
+  float* best_state;
+  float* best_cov;
+  unsigned long long* counters;
+  int32_t* queue;
+  Geom g;
+};
+
+__device__ __forceinline__ uint64_t make_key(int nhits, float chi2, int parent, uint32_t hit) {
+  const uint64_t nh = static_cast<uint64_t>(63 - nhits) & 63u;
+  const uint64_t cb = static_cast<uint64_t>(__float_as_uint(chi2) & 0x7FFFFFFFu);
+  return (nh << 58) | (cb << 27) | (static_cast<uint64_t>(parent & 7) << 24) | (hit & kHole);
+}
+
+__device__ __forceinline__ int key_nhits(uint64_t k) { return 63 - static_cast<int>(k >> 58); }
+__device__ __forceinline__ float key_chi2(uint64_t k) {
+  return __uint_as_float(static_cast<uint32_t>((k >> 27) & 0x7FFFFFFFu));
+}
+__device__ __forceinline__ int key_parent(uint64_t k) { return static_cast<int>((k >> 24) & 7u); }
+__device__ __forceinline__ uint32_t key_hit(uint64_t k) { return static_cast<uint32_t>(k & kHole); }
+
+template <int G>
+__device__ __forceinline__ uint64_t group_min(uint64_t k) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    const uint64_t o = __shfl_xor(k, off);
+    k = o < k ? o : k;
+  }
+  return k;
+}
+
+__device__ __forceinline__ int phi_bin_f(float phi, int n_phi) {
+  int b = static_cast<int>(floorf((phi + 3.14159265358979f) * (static_cast<float>(n_phi) * 0.159154943091895f)));
+  return b < 0 ? 0 : (b > n_phi - 1 ? n_phi - 1 : b);
+}
+
+__device__ __forceinline__ int eta_bin_f(float z, float R, float emax, int n_eta) {
+  const float eta = asinhf(z / R);
+  int b = static_cast<int>(floorf((eta + emax) * static_cast<float>(n_eta) / (2.f * emax)));
+  return b < 0 ? 0 : (b > n_eta - 1 ? n_eta - 1 : b);
+}
+
+__device__ __forceinline__ float wrap_pi(float a) {
+  if (a >= 3.14159265358979f) a -= 6.28318530717959f;
+  if (a < -3.14159265358979f) a += 6.28318530717959f;
+  return a;
+}
+
+template <int G>
+__device__ void build_tile(const BuildP& p, int64_t tile) {
+  constexpr int SPW = 64 / G;  // seeds per wave
+  const int lane = threadIdx.x & 63;
+  const int slot = lane % G;
+  const int gbase = lane - slot;
+  const int64_t s = tile * SPW + lane / G;
+  const bool seed_ok = s < p.n_seeds;
+  const int L = p.g.n_layers;
+  const int N = p.max_cands;
+  // event of this seed
+  int ev = 0;
+  if (seed_ok) {
+    int lo = 0, hi = p.n_events;  // seed_offsets[lo] <= s < seed_offsets[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (p.seed_offsets[mid] <= s) lo = mid; else hi = mid;
+    }
+    ev = lo;
+  }
+  const float qf = seed_ok ? static_cast<float>(p.seed_charge[s]) : 1.f;
+  const float a = -qf * kCLight * p.g.bz;
+  float st[6], cv[21];
+  int32_t status = 0;
+  if (seed_ok && slot == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) st[k] = p.seed_state[k * p.ld_seed + s];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) cv[k] = p.seed_cov[k * p.ld_seed + s];
+    status = finite6_21(st, cv) ? 0 : ST_NONFINITE;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) st[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 21; ++k) cv[k] = 0.f;
+  }
+  float chi2 = 0.f;
+  int nhits = 3;
+  int nc = seed_ok ? 1 : 0;  // candidates of this seed (same in all its lanes)
+  uint64_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0;
+
+  for (int l = p.first_layer; l < L; ++l) {
+    const bool active = slot < nc;
+    const int64_t el = static_cast<int64_t>(ev) * L + l;
+    // ---- propagate (material of the layer the candidate sits on, then the crossing)
+    float ps[6], pc[21];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ps[k] = st[k];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) pc[k] = cv[k];
+    int32_t pstat = status;
+    if (active && status == 0) {
+      int32_t r = material(ps, pc, p.g.x_over_x0[l - 1], p.g.eloss_per_x0, p.g.mass);
+      if (!r) r = propagate(ps, pc, a, p.g.r[l], p.g.z_half[l]);
+      if (r) {
+        pstat = r;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ps[k] = st[k];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) pc[k] = cv[k];
+      }
+      n_steps++;
+    }
+    // ---- scan the window's bins, keep the best N children of this candidate
+    float lkey[G];
+    int32_t lidx[G], lslot[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      lkey[t] = INFINITY;
+      lidx[t] = 0x7FFFFFFF;
+      lslot[t] = 0;
+    }
+    int cnt = 0;
+    if (active && pstat == 0) {
+      const float R = p.g.r[l];
+      const float irp = __frsqrt_rn(ps[0] * ps[0] + ps[1] * ps[1]);
+      const float tx = -ps[1] * irp, ty = ps[0] * irp;
+      const float ctt = tx * tx * pc[0] + 2.f * tx * ty * pc[1] + ty * ty * pc[2];
+      const float rtt = ctt + p.layer_vmax[2 * el];
+      const float rzz = pc[5] + p.layer_vmax[2 * el + 1];
+      const float fac = 1.f + p.margin;
+      const float wt = sqrtf(p.chi2_cut * rtt) * fac;
+      const float wz = sqrtf(p.chi2_cut * rzz) * fac;
+      const float sphi = wt / R;
+      int ip0 = 0, nspan = p.n_phi;
+      if (sphi < 1.f) {
+        const float dphi = asinf(sphi);
+        if (dphi < 1.5707963f) {
+          const float php = atan2f(ps[1], ps[0]);
+          ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
+          const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
+          nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
+        }
+      }
+      const float emax = asinhf(p.g.z_half[l] / R);
+      const int ie0 = eta_bin_f(ps[2] - wz, R, emax, p.n_eta);
+      const int ie1 = eta_bin_f(ps[2] + wz, R, emax, p.n_eta);
+      const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
+      const float4* recs = reinterpret_cast<const float4*>(p.binned);
+      for (int ie = ie0; ie <= ie1; ++ie) {
+        const int row = ie * p.n_phi;
+        const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
+        const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
+        for (int seg = 0; seg < 2; ++seg) {
+          int j0, j1;
+          if (seg == 0) {
+            j0 = bo[row + ip0];
+            j1 = bo[row + first_end];
+          } else {
+            if (wrap_end <= 0) break;
+            j0 = bo[row];
+            j1 = bo[row + wrap_end];
+          }
+          for (int j = j0; j < j1; ++j) {
+            const float4 h = recs[static_cast<int64_t>(j) * 3];
+            const float dx = h.x - ps[0], dy = h.y - ps[1], dz = h.z - ps[2];
+            n_box++;
+            if (fabsf(tx * dx + ty * dy) > wt || fabsf(dz) > wz) continue;
+            const float4 c0 = recs[static_cast<int64_t>(j) * 3 + 1];
+            const float4 c1 = recs[static_cast<int64_t>(j) * 3 + 2];
+            const float m[3] = {h.x, h.y, h.z};
+            const float v[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
+            float ri[6], rr[3], c2;
+            n_chi2++;
+            if (chi2_of(ps, pc, m, v, ri, rr, c2)) continue;
+            if (!(c2 < p.chi2_cut)) continue;
+            n_comp++;
+            float nk = chi2 + fmaxf(c2, 0.f);
+            int32_t ni = __float_as_int(h.w);
+            int32_t nj = j;
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+              const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
+              const float tk = lkey[t];
+              const int32_t ti = lidx[t], tj = lslot[t];
+              lkey[t] = sw ? nk : tk;
+              lidx[t] = sw ? ni : ti;
+              lslot[t] = sw ? nj : tj;
+              nk = sw ? tk : nk;
+              ni = sw ? ti : ni;
+              nj = sw ? tj : nj;
+            }
+            cnt = cnt + 1 < N ? cnt + 1 : N;
+          }
+        }
+      }
+    }
+    // ---- merge the seed's lists: N rounds of a G-lane minimum of the rank key
+    bool hole_left = active;
+    uint64_t mine = ~0ull;  // the child that becomes this slot's candidate
+    int32_t mine_slot = -1;
+    int new_nc = 0;
+    for (int r = 0; r < N; ++r) {
+      uint64_t k = ~0ull;
+      const bool has_hit = active && pstat == 0 && cnt > 0;
+      if (has_hit)
+        k = make_key(nhits + 1, lkey[0], slot, static_cast<uint32_t>(lidx[0]));
+      else if (hole_left)
+        k = make_key(nhits, chi2, slot, kHole);
+      const uint64_t kmin = group_min<G>(k);
+      const int winner = gbase + key_parent(kmin);
+      const int32_t wslot = __shfl(has_hit ? lslot[0] : -1, winner);
+      if (kmin != ~0ull) {
+        new_nc = r + 1;
+        if (slot == r) {
+          mine = kmin;
+          mine_slot = wslot;
+        }
+        if (k == kmin) {
+          if (has_hit) {
+#pragma unroll
+            for (int t = 0; t + 1 < G; ++t) {
+              lkey[t] = lkey[t + 1];
+              lidx[t] = lidx[t + 1];
+              lslot[t] = lslot[t + 1];
+            }
+            lkey[G - 1] = INFINITY;
+            cnt--;
+          } else {
+            hole_left = false;
+          }
+        }
+      }
+    }
+    // ---- update the survivors from their parent's propagated state
+    const int src = gbase + (mine != ~0ull ? key_parent(mine) : slot);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) st[k] = __shfl(ps[k], src);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) cv[k] = __shfl(pc[k], src);
+    status = __shfl(pstat, src);
+    if (mine != ~0ull) {
+      nhits = key_nhits(mine);
+      chi2 = key_chi2(mine);
+      const uint32_t hid = key_hit(mine);
+      if (hid != kHole && status == 0) {
+        const float4* recs = reinterpret_cast<const float4*>(p.binned);
+        const float4 h = recs[static_cast<int64_t>(mine_slot) * 3];
+        const float4 c0 = recs[static_cast<int64_t>(mine_slot) * 3 + 1];
+        const float4 c1 = recs[static_cast<int64_t>(mine_slot) * 3 + 2];
+        const float m[3] = {h.x, h.y, h.z};
+        const float v[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
+        float dc2;
+        const int32_t r = update(st, cv, m, v, dc2);
+        if (r) status = r;
+        n_upd++;
+      }
+      p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + slot] =
+          static_cast<int32_t>((static_cast<uint32_t>(key_parent(mine)) << 24) | hid);
+    }
+    nc = new_nc;
+  }
+  // ---- outputs
+  if (seed_ok) {
+    if (slot == 0) p.n_cands[s] = nc;
+    if (slot < N) {
+      const bool live = slot < nc;
+      p.cand_chi2[s * N + slot] = live ? chi2 : 0.f;
+      p.cand_nhits[s * N + slot] = live ? nhits : 0;
+      p.cand_status[s * N + slot] = live ? status : 0;
+    }
+    if (slot == 0 && p.best_state) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) p.best_state[k * p.ld_seed + s] = st[k];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) p.best_cov[k * p.ld_seed + s] = cv[k];
+    }
+  }
+  // backtrack the parent chain in place: at each layer every lane reads its
+  // record before any lane of the wave writes that layer (data dependence)
+  int kk = slot;
+  const bool live = seed_ok && slot < nc;
+  for (int l = L - 1; l >= p.first_layer; --l) {
+    int32_t out = -1;
+    int64_t at = static_cast<int64_t>(l) * p.n_seeds * N + s * N + slot;
+    if (live) {
+      const uint32_t rec = static_cast<uint32_t>(p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + kk]);
+      const uint32_t hid = rec & kHole;
+      kk = static_cast<int>(rec >> 24);
+      out = (hid == kHole) ? -1 : static_cast<int32_t>(p.layer_offsets[static_cast<int64_t>(ev) * L + l] + hid);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (seed_ok && slot < N) p.cand_hits[at] = out;
+  }
+  if (seed_ok && slot < N) {
+    for (int l = 0; l < p.first_layer; ++l) {
+      int32_t out = -1;
+      if (live && l < 3) out = p.seed_hits[l * p.ld_seed + s];
+      p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + slot] = out;
+    }
+  }
+  if (p.counters) {
+    uint64_t v[KF_BUILD_COUNTERS] = {n_box, n_chi2, n_comp, n_steps, n_upd};
+#pragma unroll
+    for (int i = 0; i < KF_BUILD_COUNTERS; ++i) {
+      uint64_t x = v[i];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+      if (lane == 0 && x) atomicAdd(&p.counters[i], static_cast<unsigned long long>(x));
+    }
+  }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) build_tiled_kernel(BuildP p) {
+  const int64_t tile = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  build_tile<G>(p, tile);
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t n_tiles) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int32_t t = 0;
+    if (lane == 0) t = atomicAdd(p.queue, 1);
+    t = __shfl(t, 0);
+    if (t >= n_tiles) break;
+    build_tile<G>(p, t);
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+int lanes_for(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8; }
+
+}  // namespace
+
+using kfh::set_error;
+
+extern "C" {
+
+size_t kf_bin_hits_workspace_size(int64_t ldh) { return static_cast<size_t>(ldh > 0 ? ldh : 0) * 4u; }
+
+int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
+  if (int32_t rc = kfh::enter(ctx)) return rc;
+  if (!a) return set_error(KF_ERR_INVALID_ARG, "null args");
+  if (!ctx->has_geometry) return set_error(KF_ERR_GEOMETRY, "no geometry set");
+  if (a->n_events < 0 || a->ldh < 0) return set_error(KF_ERR_INVALID_ARG, "bad sizes");
+  if (a->n_phi < 1 || a->n_eta < 1 || a->n_phi * a->n_eta > kMaxBins)
+    return set_error(KF_ERR_INVALID_ARG, "need 1 <= n_phi * n_eta <= %d", kMaxBins);
+  if (a->ldh >= (int64_t(1) << 31)) return set_error(KF_ERR_INVALID_ARG, "too many hits for int32 slots");
+  if (a->n_events == 0) return KF_OK;
+  if (!a->layer_offsets || !a->hit_pos || !a->hit_cov || !a->bin_offsets || !a->perm || !a->binned ||
+      !a->layer_vmax)
+    return set_error(KF_ERR_INVALID_ARG, "null array");
+  if (!a->workspace || a->workspace_bytes < kf_bin_hits_workspace_size(a->ldh))
+    return set_error(KF_ERR_WORKSPACE, "workspace of %zu bytes needed", kf_bin_hits_workspace_size(a->ldh));
+  const int L = ctx->geom.n_layers;
+  const int64_t n_el = a->n_events * L;
+  if (n_el > INT32_MAX) return set_error(KF_ERR_INVALID_ARG, "too many (event, layer) pairs");
+  bin_kernel<<<static_cast<unsigned>(n_el), kBinThreads, 0, kfh::stream_of(a->stream)>>>(
+      L, a->layer_offsets, a->hit_pos, a->hit_cov, a->ldh, a->n_phi, a->n_eta, ctx->dgeom,
+      static_cast<int32_t*>(a->workspace), a->bin_offsets, a->perm, a->binned, a->layer_vmax);
+  return kfh::check_hip(hipGetLastError(), "bin_kernel launch");
+}
+
+size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_seeds) {
+  (void)n_seeds;
+  if (cfg && cfg->mode == KF_BUILD_PERSISTENT) return 256;
+  return 0;
+}
+
+int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
+  if (int32_t rc = kfh::enter(ctx)) return rc;
+  if (!cfg || !a) return set_error(KF_ERR_INVALID_ARG, "null args");
+  if (!ctx->has_geometry) return set_error(KF_ERR_GEOMETRY, "no geometry set");
+  const int L = ctx->geom.n_layers;
+  if (cfg->max_cands < 1 || cfg->max_cands > 8) return set_error(KF_ERR_INVALID_ARG, "max_cands must be 1..8");
+  if (!(cfg->chi2_cut > 0.f)) return set_error(KF_ERR_INVALID_ARG, "chi2_cut must be > 0");
+  if (cfg->n_phi < 1 || cfg->n_eta < 1 || cfg->n_phi * cfg->n_eta > kMaxBins)
+    return set_error(KF_ERR_INVALID_ARG, "bad bin counts");
+  if (!(cfg->window_margin >= 0.f)) return set_error(KF_ERR_INVALID_ARG, "window_margin must be >= 0");
+  if (cfg->mode != KF_BUILD_TILED && cfg->mode != KF_BUILD_PERSISTENT)
+    return set_error(KF_ERR_INVALID_ARG, "unknown mode %d", cfg->mode);
+  if (cfg->window_mode != KF_WINDOW_PLAIN) return set_error(KF_ERR_INVALID_ARG, "window mode not available");
+  if (a->n_events < 0 || a->n_seeds < 0 || a->ld_seed < a->n_seeds)
+    return set_error(KF_ERR_INVALID_ARG, "bad sizes");
+  if (a->first_layer < 3 || a->first_layer > L) return set_error(KF_ERR_INVALID_ARG, "first_layer must be in [3, L]");
+  if (a->n_seeds == 0) return KF_OK;
+  if (a->n_events < 1 || a->n_events > INT32_MAX) return set_error(KF_ERR_INVALID_ARG, "bad n_events");
+  if (!a->seed_offsets || !a->seed_state || !a->seed_cov || !a->seed_charge || !a->seed_hits || !a->layer_offsets ||
+      !a->bin_offsets || !a->binned || !a->layer_vmax || !a->n_cands || !a->cand_hits || !a->cand_chi2 ||
+      !a->cand_nhits || !a->cand_status)
+    return set_error(KF_ERR_INVALID_ARG, "null array");
+  if ((a->best_state == nullptr) != (a->best_cov == nullptr))
+    return set_error(KF_ERR_INVALID_ARG, "best_state and best_cov go together");
+  if (a->n_seeds * static_cast<int64_t>(cfg->max_cands) * L > INT64_MAX / 8)
+    return set_error(KF_ERR_INVALID_ARG, "too many seeds");
+  BuildP p;
+  p.n_seeds = a->n_seeds;
+  p.ld_seed = a->ld_seed;
+  p.n_events = static_cast<int32_t>(a->n_events);
+  p.first_layer = a->first_layer;
+  p.max_cands = cfg->max_cands;
+  p.n_phi = cfg->n_phi;
+  p.n_eta = cfg->n_eta;
+  p.chi2_cut = cfg->chi2_cut;
+  p.margin = cfg->window_margin;
+  p.seed_offsets = a->seed_offsets;
+  p.seed_state = a->seed_state;
+  p.seed_cov = a->seed_cov;
+  p.seed_charge = a->seed_charge;
+  p.seed_hits = a->seed_hits;
+  p.layer_offsets = a->layer_offsets;
+  p.bin_offsets = a->bin_offsets;
+  p.binned = a->binned;
+  p.layer_vmax = a->layer_vmax;
+  p.n_cands = a->n_cands;
+  p.cand_hits = a->cand_hits;
+  p.cand_chi2 = a->cand_chi2;
+  p.cand_nhits = a->cand_nhits;
+  p.cand_status = a->cand_status;
+  p.best_state = a->best_state;
+  p.best_cov = a->best_cov;
+  p.counters = reinterpret_cast<unsigned long long*>(a->counters);
+  p.queue = nullptr;
+  p.g = ctx->dgeom;
+  const int G = lanes_for(cfg->max_cands);
+  const int64_t spw = 64 / G;
+  const int64_t n_tiles = (a->n_seeds + spw - 1) / spw;
+  const int wpb = cfg->waves_per_block > 0 ? cfg->waves_per_block : 4;
+  if (wpb > 4) return set_error(KF_ERR_INVALID_ARG, "waves_per_block must be 1..4");
+  hipStream_t stream = kfh::stream_of(a->stream);
+  if (cfg->mode == KF_BUILD_TILED) {
+    const unsigned grid = static_cast<unsigned>((n_tiles + wpb - 1) / wpb);
+    const unsigned block = 64u * wpb;
+    switch (G) {
+      case 1: build_tiled_kernel<1><<<grid, block, 0, stream>>>(p); break;
+      case 2: build_tiled_kernel<2><<<grid, block, 0, stream>>>(p); break;
+      case 4: build_tiled_kernel<4><<<grid, block, 0, stream>>>(p); break;
+      default: build_tiled_kernel<8><<<grid, block, 0, stream>>>(p); break;
+    }
+    return kfh::check_hip(hipGetLastError(), "build_tiled_kernel launch");
+  }
+  if (!a->workspace || a->workspace_bytes < kf_build_workspace_size(cfg, a->n_seeds))
+    return set_error(KF_ERR_WORKSPACE, "persistent mode needs kf_build_workspace_size() bytes of workspace");
+  p.queue = static_cast<int32_t*>(a->workspace);
+  fill_i32_kernel<<<1, 64, 0, stream>>>(p.queue, 1, 0);
+  const int bpc = cfg->blocks_per_cu > 0 ? cfg->blocks_per_cu : 2;
+  const unsigned grid = static_cast<unsigned>(ctx->num_cus * bpc);
+  const unsigned block = 64u * wpb;
+  switch (G) {
+    case 1: build_persistent_kernel<1><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    case 2: build_persistent_kernel<2><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    case 4: build_persistent_kernel<4><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    default: build_persistent_kernel<8><<<grid, block, 0, stream>>>(p, n_tiles); break;
+  }
+  return kfh::check_hip(hipGetLastError(), "build_persistent_kernel launch");
+}
+
+}  // extern "C"

@@ -266,64 +266,80 @@ KF_DEV int32_t chi2_of(const float s[6], const float c[21], const float m[3], co
   return 0;
 }
 
-// Kalman update with the hit (m, v).  The covariance uses the algebraically
-// identical forms C_pos'' = A R^-1 V, C_mom,pos'' = B R^-1 V and
+// Kalman update with the hit (m, v), computed in precision T (the state and
+// covariance stay float32 in registers and HBM).  The covariance uses the
+// algebraically identical forms C_pos'' = A R^-1 V, C_mom,pos'' = B R^-1 V and
 // C_mom'' = D - B R^-1 B^T (A, B, D = position, cross and momentum blocks),
-// which avoid the cancellation of A - A R^-1 A when the prior is vague.
-KF_DEV int32_t update(float s[6], float c[21], const float m[3], const float v[6], float& chi2) {
-  float ri[6], r[3];
-  int32_t st = chi2_of(s, c, m, v, ri, r, chi2);
-  if (st) return st;
-  // R^-1 r
-  const float q0 = ri[0] * r[0] + ri[1] * r[1] + ri[3] * r[2];
-  const float q1 = ri[1] * r[0] + ri[2] * r[1] + ri[4] * r[2];
-  const float q2 = ri[3] * r[0] + ri[4] * r[1] + ri[5] * r[2];
-  // full R^-1 and V
-  const float Ri[3][3] = {{ri[0], ri[1], ri[3]}, {ri[1], ri[2], ri[4]}, {ri[3], ri[4], ri[5]}};
-  const float V[3][3] = {{v[0], v[1], v[3]}, {v[1], v[2], v[4]}, {v[3], v[4], v[5]}};
-  // M = R^-1 V
-  float M[3][3];
+// which avoid the cancellation of A - A R^-1 A when the prior is vague.  The
+// remaining cancellation in D - B R^-1 B^T and the 3x3 inverse are what limit
+// a float32 update; gfx950 runs FP64 FMA at the unpacked FP32 rate, so the fit
+// and the build's survivor update use T = double.
+template <typename T>
+KF_DEV int32_t update_t(float s[6], float c[21], const float m[3], const float v[6], float& chi2_out) {
+  const T a = T(c[0]) + T(v[0]), b = T(c[1]) + T(v[1]), d = T(c[2]) + T(v[2]);
+  const T e = T(c[3]) + T(v[3]), f = T(c[4]) + T(v[4]), g = T(c[5]) + T(v[5]);
+  const T i00 = d * g - f * f;
+  const T i10 = e * f - b * g;
+  const T i20 = b * f - d * e;
+  const T det = a * i00 + b * i10 + e * i20;
+  const T m2 = a * d - b * b;
+  if (!(a > T(0)) || !(m2 > T(0)) || !(det > T(0))) return ST_NOT_PD;
+  const T id = T(1) / det;
+  const T Ri[3][3] = {{i00 * id, i10 * id, i20 * id},
+                      {i10 * id, (a * g - e * e) * id, (b * e - a * f) * id},
+                      {i20 * id, (b * e - a * f) * id, m2 * id}};
+  const T r[3] = {T(m[0]) - T(s[0]), T(m[1]) - T(s[1]), T(m[2]) - T(s[2])};
+  T q[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) q[i] = Ri[i][0] * r[0] + Ri[i][1] * r[1] + Ri[i][2] * r[2];
+  const T chi2 = r[0] * q[0] + r[1] * q[1] + r[2] * q[2];
+  const T V[3][3] = {{T(v[0]), T(v[1]), T(v[3])}, {T(v[1]), T(v[2]), T(v[4])}, {T(v[3]), T(v[4]), T(v[5])}};
+  T M[3][3];  // R^-1 V
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) M[i][j] = Ri[i][0] * V[0][j] + Ri[i][1] * V[1][j] + Ri[i][2] * V[2][j];
-  // blocks of the prior: A (pos), B (mom x pos), D (mom)
-  float A[3][3], B[3][3];
+  T A[3][3], B[3][3], D[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      A[i][j] = c[tri(i, j)];
-      B[i][j] = c[tri(i + 3, j)];
+      A[i][j] = T(c[tri(i, j)]);
+      B[i][j] = T(c[tri(i + 3, j)]);
+      D[i][j] = T(c[tri(i + 3, j + 3)]);
     }
-  // G = B R^-1
-  float G[3][3];
+  T G[3][3];  // B R^-1
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) G[i][j] = B[i][0] * Ri[0][j] + B[i][1] * Ri[1][j] + B[i][2] * Ri[2][j];
-  // state
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    s[i] += A[i][0] * q0 + A[i][1] * q1 + A[i][2] * q2;
-    s[i + 3] += B[i][0] * q0 + B[i][1] * q1 + B[i][2] * q2;
+    s[i] = static_cast<float>(T(s[i]) + (A[i][0] * q[0] + A[i][1] * q[1] + A[i][2] * q[2]));
+    s[i + 3] = static_cast<float>(T(s[i + 3]) + (B[i][0] * q[0] + B[i][1] * q[1] + B[i][2] * q[2]));
   }
-  // covariance
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) c[tri(i, j)] = A[i][0] * M[0][j] + A[i][1] * M[1][j] + A[i][2] * M[2][j];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) c[tri(i + 3, j)] = B[i][0] * M[0][j] + B[i][1] * M[1][j] + B[i][2] * M[2][j];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j <= i; ++j)
-      c[tri(i + 3, j + 3)] -= G[i][0] * B[j][0] + G[i][1] * B[j][1] + G[i][2] * B[j][2];
+      c[tri(i, j)] = static_cast<float>(A[i][0] * M[0][j] + A[i][1] * M[1][j] + A[i][2] * M[2][j]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      c[tri(i + 3, j)] = static_cast<float>(B[i][0] * M[0][j] + B[i][1] * M[1][j] + B[i][2] * M[2][j]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j)
+      c[tri(i + 3, j + 3)] = static_cast<float>(D[i][j] - (G[i][0] * B[j][0] + G[i][1] * B[j][1] + G[i][2] * B[j][2]));
+  chi2_out = static_cast<float>(chi2);
   if (!finite6_21(s, c)) return ST_NONFINITE;
   return 0;
+}
+
+KF_DEV int32_t update(float s[6], float c[21], const float m[3], const float v[6], float& chi2) {
+  return update_t<double>(s, c, m, v, chi2);
 }
 
 }  // namespace kfd

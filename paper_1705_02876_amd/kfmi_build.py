@@ -1,5 +1,151 @@
-"""Declarations and wrappers of the hit-binning and building calls (filled in with the build path)."""
+"""Binding of the hit-binning and building calls of include/kfmi.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+
+BINNED_FLOATS = 12
+BUILD_TILED, BUILD_PERSISTENT = 0, 1
+WINDOW_PLAIN, WINDOW_LEARNED = 0, 1
+
+
+class kf_bin_args(C.Structure):
+    _fields_ = [
+        ("n_events", C.c_int64), ("layer_offsets", C.c_void_p), ("hit_pos", C.c_void_p), ("hit_cov", C.c_void_p),
+        ("ldh", C.c_int64), ("n_phi", C.c_int32), ("n_eta", C.c_int32), ("bin_offsets", C.c_void_p),
+        ("perm", C.c_void_p), ("binned", C.c_void_p), ("layer_vmax", C.c_void_p), ("workspace", C.c_void_p),
+        ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
+    ]
+
+
+class kf_build_cfg(C.Structure):
+    _fields_ = [
+        ("max_cands", C.c_int32), ("chi2_cut", C.c_float), ("n_phi", C.c_int32), ("n_eta", C.c_int32),
+        ("window_margin", C.c_float), ("mode", C.c_int32), ("window_mode", C.c_int32),
+        ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
+    ]
+
+
+class kf_build_args(C.Structure):
+    _fields_ = [
+        ("n_events", C.c_int64), ("n_seeds", C.c_int64), ("ld_seed", C.c_int64), ("first_layer", C.c_int32),
+        ("seed_offsets", C.c_void_p), ("seed_state", C.c_void_p), ("seed_cov", C.c_void_p),
+        ("seed_charge", C.c_void_p), ("seed_hits", C.c_void_p), ("layer_offsets", C.c_void_p),
+        ("bin_offsets", C.c_void_p), ("binned", C.c_void_p), ("layer_vmax", C.c_void_p),
+        ("n_cands", C.c_void_p), ("cand_hits", C.c_void_p), ("cand_chi2", C.c_void_p),
+        ("cand_nhits", C.c_void_p), ("cand_status", C.c_void_p), ("best_state", C.c_void_p),
+        ("best_cov", C.c_void_p), ("counters", C.c_void_p), ("workspace", C.c_void_p),
+        ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
+    ]
 
 
 def declare(lib):
+    P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.kf_bin_hits_workspace_size.restype = C.c_size_t
+    lib.kf_bin_hits_workspace_size.argtypes = [I64]
+    lib.kf_bin_hits.restype = I32
+    lib.kf_bin_hits.argtypes = [P, P]
+    lib.kf_build_workspace_size.restype = C.c_size_t
+    lib.kf_build_workspace_size.argtypes = [P, I64]
+    lib.kf_build.restype = I32
+    lib.kf_build.argtypes = [P, P, P]
     return lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16, out=None, workspace=None,
+             stream=None):
+    """kf_bin_hits.  Returns dict(bin_offsets, perm, binned, layer_vmax) of device tensors."""
+    import torch
+    from . import kfmi
+    lib = kfmi.load_library()
+    ldh = hit_pos.shape[1]
+    L = ctx.n_layers
+    dev = hit_pos.device
+    if out is None:
+        out = dict(bin_offsets=torch.empty(n_events * L, n_phi * n_eta + 1, dtype=torch.int32, device=dev),
+                   perm=torch.empty(max(ldh, 1), dtype=torch.int32, device=dev),
+                   binned=torch.empty(max(ldh, 1), BINNED_FLOATS, dtype=torch.float32, device=dev),
+                   layer_vmax=torch.empty(n_events * L, 2, dtype=torch.float32, device=dev))
+    wsb = lib.kf_bin_hits_workspace_size(ldh)
+    if workspace is None:
+        workspace = torch.empty(max(wsb, 4), dtype=torch.uint8, device=dev)
+    a = kf_bin_args()
+    a.n_events = n_events
+    a.layer_offsets = _ptr(layer_offsets)
+    a.hit_pos, a.hit_cov, a.ldh = _ptr(hit_pos), _ptr(hit_cov), ldh
+    a.n_phi, a.n_eta = n_phi, n_eta
+    a.bin_offsets, a.perm, a.binned, a.layer_vmax = (_ptr(out["bin_offsets"]), _ptr(out["perm"]),
+                                                       _ptr(out["binned"]), _ptr(out["layer_vmax"]))
+    a.workspace, a.workspace_bytes = _ptr(workspace), workspace.numel()
+    a.stream = kfmi._stream(stream)
+    kfmi._check(lib.kf_bin_hits(ctx.h, C.byref(a)))
+    return out
+
+
+def make_cfg(max_cands=6, chi2_cut=30.0, n_phi=64, n_eta=16, window_margin=0.01, mode=BUILD_TILED,
+             window_mode=WINDOW_PLAIN, waves_per_block=0, blocks_per_cu=0):
+    return kf_build_cfg(max_cands, chi2_cut, n_phi, n_eta, window_margin, mode, window_mode, waves_per_block,
+                        blocks_per_cu)
+
+
+def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=None, counters=None, workspace=None,
+          stream=None):
+    """kf_build.  seeds: dict(offsets int64 (E+1), state (6,ld), cov (21,ld), charge int8 (S), hits int32 (3,ld), n).
+
+    Returns dict of device tensors (n_cands, cand_hits (L,S,N), cand_chi2 (S,N), cand_nhits, cand_status,
+    best_state, best_cov)."""
+    import torch
+    from . import kfmi
+    lib = kfmi.load_library()
+    S = seeds["n"]
+    ld = seeds["state"].shape[1]
+    N = cfg.max_cands
+    L = ctx.n_layers
+    dev = seeds["state"].device
+    if out is None:
+        out = dict(n_cands=torch.empty(max(S, 1), dtype=torch.int32, device=dev),
+                   cand_hits=torch.empty(L, max(S, 1), N, dtype=torch.int32, device=dev),
+                   cand_chi2=torch.empty(max(S, 1), N, dtype=torch.float32, device=dev),
+                   cand_nhits=torch.empty(max(S, 1), N, dtype=torch.int32, device=dev),
+                   cand_status=torch.empty(max(S, 1), N, dtype=torch.int32, device=dev),
+                   best_state=torch.empty(6, ld, dtype=torch.float32, device=dev),
+                   best_cov=torch.empty(21, ld, dtype=torch.float32, device=dev))
+    wsb = lib.kf_build_workspace_size(C.byref(cfg), S)
+    if workspace is None and wsb > 0:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    a = kf_build_args()
+    a.n_events, a.n_seeds, a.ld_seed, a.first_layer = n_events, S, ld, first_layer
+    a.seed_offsets, a.seed_state, a.seed_cov = _ptr(seeds["offsets"]), _ptr(seeds["state"]), _ptr(seeds["cov"])
+    a.seed_charge, a.seed_hits = _ptr(seeds["charge"]), _ptr(seeds["hits"])
+    a.layer_offsets = _ptr(layer_offsets)
+    a.bin_offsets, a.binned, a.layer_vmax = _ptr(bins["bin_offsets"]), _ptr(bins["binned"]), _ptr(bins["layer_vmax"])
+    a.n_cands, a.cand_hits, a.cand_chi2 = _ptr(out["n_cands"]), _ptr(out["cand_hits"]), _ptr(out["cand_chi2"])
+    a.cand_nhits, a.cand_status = _ptr(out["cand_nhits"]), _ptr(out["cand_status"])
+    a.best_state, a.best_cov = _ptr(out.get("best_state")), _ptr(out.get("best_cov"))
+    a.counters = _ptr(counters)
+    if workspace is not None:
+        a.workspace, a.workspace_bytes = _ptr(workspace), workspace.numel()
+    a.stream = kfmi._stream(stream)
+    kfmi._check(lib.kf_build(ctx.h, C.byref(cfg), C.byref(a)))
+    return out
+
+
+def upload_problem(prob, dtype_note=None):
+    """Device tensors of a synth.BuildProblem in the kfmi.h layouts (float32)."""
+    import numpy as np
+    import torch
+    from . import synth as S
+    dev = "cuda"
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32))).to(dev)
+    seeds = dict(
+        offsets=torch.from_numpy(np.asarray(prob.seed_offsets, np.int64)).to(dev),
+        state=f32(prob.seed_state.T), cov=f32(S.pack6(prob.seed_cov).T),
+        charge=torch.from_numpy(prob.seed_q.astype(np.int8)).to(dev),
+        hits=torch.from_numpy(np.ascontiguousarray(prob.seed_hits.T.astype(np.int32))).to(dev),
+        n=prob.seed_state.shape[0])
+    hits = dict(layer_offsets=torch.from_numpy(np.asarray(prob.layer_hit_offsets, np.int64)).to(dev),
+                pos=f32(prob.hit_pos.T), cov=f32(prob.hit_cov.T))
+    return seeds, hits

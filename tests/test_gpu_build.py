@@ -1,0 +1,186 @@
+"""GPU parity of hit binning and combinatorial building against the FP64 oracle (through the C ABI).
+
+Binning is integer work and must match bit for bit.  For building, the
+candidate lists (hit indices, number of candidates, number of hits) must match
+exactly on decision-stable seeds: seeds whose every chi2 decision and every
+rank comparison around the cut-off is farther from its threshold than the
+chi2 tolerance (1e-3 relative) in the oracle's own run.  chi2 must agree to
+1e-3 and the best candidate's state to 1e-4 on those seeds.  Unstable seeds
+are counted and must be rare.
+"""
+import numpy as np
+import pytest
+
+from paper_1705_02876_amd import synth as S
+
+from kfutil import check_chi2, check_params, rounded
+
+pytestmark = pytest.mark.gpu
+
+STABLE = 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1705_02876_amd import kfmi
+    assert torch.cuda.is_available()
+    c = kfmi.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_build(ctx, prob, N=6, mode=0, det32=None, counters=False):
+    import torch
+    from paper_1705_02876_amd import kfmi_build as KB
+    ctx.kf_set_geometry(det32)
+    seeds, hits = KB.upload_problem(prob)
+    bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events)
+    cfg = KB.make_cfg(max_cands=N, mode=mode)
+    cnt = torch.zeros(5, dtype=torch.int64, device="cuda") if counters else None
+    out = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, counters=cnt)
+    torch.cuda.synchronize()
+    S_ = seeds["n"]
+    res = dict(n_cands=out["n_cands"].cpu().numpy()[:S_],
+               cand_hits=np.transpose(out["cand_hits"].cpu().numpy()[:, :S_, :], (1, 2, 0)),  # (S, N, L)
+               cand_chi2=out["cand_chi2"].cpu().numpy()[:S_].astype(np.float64),
+               cand_nhits=out["cand_nhits"].cpu().numpy()[:S_],
+               cand_status=out["cand_status"].cpu().numpy()[:S_],
+               best_state=out["best_state"].cpu().numpy().T[:S_].astype(np.float64))
+    if counters:
+        res["counters"] = cnt.cpu().numpy()
+    return res, bins
+
+
+def _oracle_build(orc, prob, det32, N=6, seeds=None):
+    g = orc.geometry(det32)
+    return orc.build(g, prob, max_cands=N, mode=1, hit_pos=rounded(prob.hit_pos),
+                     hit_cov_full=S.unpack3(rounded(prob.hit_cov)), seed_state=rounded(prob.seed_state),
+                     seed_cov=S.unpack6(rounded(S.pack6(prob.seed_cov))), seeds=seeds)
+
+
+def _compare(gpu, ora, sel=None, label=""):
+    """Exact candidate lists on stable seeds; returns (n_stable, n_all, n_match_all)."""
+    n = ora["n_cands"].shape[0]
+    g = {k: (v if sel is None else v[sel]) for k, v in gpu.items() if k != "counters"}
+    stable = (ora["margin_cut"] > STABLE) & (ora["margin_rank"] > STABLE)
+    same = (g["n_cands"] == ora["n_cands"]) & np.all(g["cand_hits"] == ora["cand_hits"], axis=(1, 2)) & np.all(
+        g["cand_nhits"] == ora["cand_nhits"], axis=1)
+    bad = np.nonzero(stable & ~same)[0]
+    print(f"[build parity {label}] seeds {n}, stable {stable.sum()}, exact on all {same.sum()}, "
+          f"mismatch on stable {bad.size}", flush=True)
+    assert bad.size == 0, f"stable seeds with different candidates: {bad[:10]}"
+    ok = stable & same
+    for k in range(g["cand_chi2"].shape[1]):
+        live = ok & (ora["n_cands"] > k)
+        check_chi2(g["cand_chi2"][live, k], ora["cand_chi2"][live, k], f"cand chi2 rank {k}")
+    live = ok & (ora["cand_status"][:, 0] == 0)
+    check_params(g["best_state"][live], ora["best_state"][live], "best state")
+    assert same.mean() > 0.97, same.mean()
+    return stable.sum(), n, same.sum()
+
+
+def test_bin_hits_bit_exact(ctx, orc):
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = S.make_build_problem([700, 0, 2300, 35], det, 61)
+    _, bins = _gpu_build(ctx, prob, N=1, det32=det32)
+    g = orc.geometry(det32)
+    bo, perm, _ = orc.bin_hits(g, prob.n_events, prob.layer_hit_offsets, rounded(prob.hit_pos))
+    gbo = bins["bin_offsets"].cpu().numpy()
+    gperm = bins["perm"].cpu().numpy()[: perm.size]
+    assert np.array_equal(gbo, bo)
+    assert np.array_equal(gperm.astype(np.int64), perm)
+    rec = bins["binned"].cpu().numpy()[: perm.size]
+    hp = np.asarray(prob.hit_pos, np.float32)
+    assert np.array_equal(rec[:, :3], hp[perm])
+    lo = np.repeat(prob.layer_hit_offsets[:-1], np.diff(prob.layer_hit_offsets))
+    assert np.array_equal(rec[:, 3].view(np.int32), (perm - lo[perm]).astype(np.int32))
+    hc = np.asarray(prob.hit_cov, np.float32)
+    assert np.array_equal(rec[:, 4:10], hc[perm])
+    vm = bins["layer_vmax"].cpu().numpy()
+    nonempty = np.diff(prob.layer_hit_offsets) > 0
+    assert np.allclose(vm[nonempty, 0], det.sigma_rphi ** 2, rtol=1e-5)
+    assert np.allclose(vm[nonempty, 1], det.sigma_z ** 2, rtol=1e-5)
+
+
+@pytest.mark.parametrize("N,mode", [(6, 0), (6, 1), (1, 0), (3, 0), (8, 1)])
+def test_build_parity(ctx, orc, N, mode):
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = S.make_build_problem([800, 1500, 3, 0, 1200], det, 62)
+    gpu, _ = _gpu_build(ctx, prob, N=N, mode=mode, det32=det32)
+    ora = _oracle_build(orc, prob, det32, N=N)
+    _compare(gpu, ora, label=f"N={N} mode={mode}")
+
+
+def test_build_deterministic_and_modes_agree(ctx):
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = S.make_build_problem([2500, 700], det, 63)
+    a, _ = _gpu_build(ctx, prob, N=6, mode=0, det32=det32)
+    b, _ = _gpu_build(ctx, prob, N=6, mode=0, det32=det32)
+    c, _ = _gpu_build(ctx, prob, N=6, mode=1, det32=det32)
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+        assert np.array_equal(a[k], c[k], equal_nan=True), k
+
+
+def test_build_edge_cases(ctx, orc):
+    import torch
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = S.make_build_problem([1, 0, 5], det, 64)
+    prob.seed_state[2, 0] = np.nan  # non-finite seed: stays one stopped candidate
+    gpu, _ = _gpu_build(ctx, prob, N=6, det32=det32)
+    ora = _oracle_build(orc, prob, det32, N=6)
+    assert gpu["n_cands"][2] == 1 and gpu["cand_status"][2, 0] == 4 and ora["cand_status"][2, 0] == 4
+    assert np.array_equal(gpu["cand_hits"][2, 0, :3], prob.seed_hits[2])
+    assert (gpu["cand_hits"][2, 0, 3:] == -1).all()
+    ok = np.arange(prob.seed_state.shape[0]) != 2
+    assert np.array_equal(gpu["n_cands"][ok], ora["n_cands"][ok])
+    # empty seed list is a no-op
+    from paper_1705_02876_amd import kfmi_build as KB
+    seeds, hits = KB.upload_problem(prob)
+    seeds["n"] = 0
+    bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events)
+    KB.build(ctx, KB.make_cfg(), seeds, bins, hits["layer_offsets"], prob.n_events)
+    torch.cuda.synchronize()
+
+
+def test_build_rejects_bad_config(ctx):
+    from paper_1705_02876_amd import kfmi, kfmi_build as KB
+    det = S.detector_full()
+    prob = S.make_build_problem([10], det, 65)
+    ctx.kf_set_geometry(det.as_float32())
+    seeds, hits = KB.upload_problem(prob)
+    bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events)
+    for bad in (KB.make_cfg(max_cands=9), KB.make_cfg(max_cands=0), KB.make_cfg(chi2_cut=-1.0),
+                KB.make_cfg(mode=7)):
+        with pytest.raises(kfmi.KfError):
+            KB.build(ctx, bad, seeds, bins, hits["layer_offsets"], prob.n_events)
+    with pytest.raises(kfmi.KfError):
+        KB.build(ctx, KB.make_cfg(), seeds, bins, hits["layer_offsets"], prob.n_events, first_layer=2)
+
+
+def test_build_full_size_sampled(ctx, orc):
+    """16 events of U{5k..20k} tracks (the build workload, its launch); 600 sampled seeds against the oracle."""
+    from paper_1705_02876_amd import workloads as W
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = W.build_workload(16, det)
+    gpu, _ = _gpu_build(ctx, prob, N=6, mode=0, det32=det32, counters=True)
+    rng = np.random.Generator(np.random.PCG64(3))
+    sel = np.sort(rng.choice(prob.seed_state.shape[0], 600, replace=False))
+    ora = _oracle_build(orc, prob, det32, N=6, seeds=sel)
+    _compare(gpu, ora, sel=sel, label="full-size sample")
+    # properties over every seed: candidate counts in range, ranks ordered
+    nc = gpu["n_cands"]
+    assert ((nc >= 1) & (nc <= 6)).all()
+    nh = gpu["cand_nhits"]
+    c2 = gpu["cand_chi2"]
+    for k in range(5):
+        live = nc > k + 1
+        ordered = (nh[live, k] > nh[live, k + 1]) | ((nh[live, k] == nh[live, k + 1]) & (c2[live, k] <= c2[live, k + 1]))
+        assert ordered.all()
+    print(f"[build full-size] counters box/chi2/compatible/steps/updates = {gpu['counters']}", flush=True)
