@@ -55,6 +55,16 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def check_offsets(t, count, limit, name):
+    """Host check of a device offset array: `count` + 1 ascending int64 values in [0, limit]."""
+    import torch
+    if t.dtype != torch.int64 or t.numel() < count + 1:
+        raise ValueError(f"{name}: need {count + 1} int64 offsets")
+    h = t[: count + 1].cpu()
+    if int(h[0]) < 0 or int(h[-1]) > limit or bool((h[1:] < h[:-1]).any()):
+        raise ValueError(f"{name}: offsets must ascend within [0, {limit}]")
+
+
 def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16, out=None, workspace=None,
              stream=None):
     """kf_bin_hits.  Returns dict(bin_offsets, perm, binned, layer_vmax) of device tensors."""
@@ -64,6 +74,7 @@ def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16,
     ldh = hit_pos.shape[1]
     L = ctx.n_layers
     dev = hit_pos.device
+    check_offsets(layer_offsets, n_events * L, ldh, "layer_offsets")
     if out is None:
         out = dict(bin_offsets=torch.empty(n_events * L, n_phi * n_eta + 1, dtype=torch.int32, device=dev),
                    perm=torch.empty(max(ldh, 1), dtype=torch.int32, device=dev),
@@ -105,6 +116,11 @@ def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=Non
     N = cfg.max_cands
     L = ctx.n_layers
     dev = seeds["state"].device
+    if S > 0:
+        check_offsets(seeds["offsets"], n_events, S, "seed_offsets")
+        if int(seeds["offsets"][n_events].item()) != S or int(seeds["offsets"][0].item()) != 0:
+            raise ValueError("seed_offsets must start at 0 and end at n_seeds")
+        check_offsets(layer_offsets, n_events * L, bins["binned"].shape[0], "layer_offsets")
     if out is None:
         out = dict(n_cands=torch.empty(max(S, 1), dtype=torch.int32, device=dev),
                    cand_hits=torch.empty(L, max(S, 1), N, dtype=torch.int32, device=dev),
