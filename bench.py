@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--tracks", type=int, default=2_000_000)
     ap.add_argument("--events", type=int, default=64)
     ap.add_argument("--build-mode", choices=["tiled", "persistent"], default="persistent")
+    ap.add_argument("--build-precision", choices=["f32", "f64"], default="f64")
+    ap.add_argument("--fit-fp64", action="store_true", help="double-precision registers in the fit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -185,7 +187,8 @@ def main():
     seeds, hits = KB.upload_problem(bp)
     N = 6
     mode = KB.BUILD_PERSISTENT if args.build_mode == "persistent" else KB.BUILD_TILED
-    cfg = KB.make_cfg(max_cands=N, mode=mode)
+    cfg = KB.make_cfg(max_cands=N, mode=mode,
+                      precision=KB.PREC_F64 if args.build_precision == "f64" else KB.PREC_F32)
     bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events)
     bws_bytes = kfmi.load_library().kf_bin_hits_workspace_size(hits["pos"].shape[1])
     bws = torch.empty(max(bws_bytes, 4), dtype=torch.uint8, device=dev)
@@ -194,7 +197,7 @@ def main():
     torch.cuda.synchronize()
 
     def fit_step():
-        ctx.kf_fit(st_in, cv_in, q, hidx, hpos, hcov, st_out, cv_out, chi2, nh, stat)
+        ctx.kf_fit(st_in, cv_in, q, hidx, hpos, hcov, st_out, cv_out, chi2, nh, stat, fp64=args.fit_fp64)
 
     def bin_step():
         KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events, out=bins, workspace=bws)
@@ -266,14 +269,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (Kalman update f64)",
+        "dtype": ("f64 registers / f32 storage" if args.fit_fp64 else "f32 (Kalman update f64)") + " fit; "
+                 + ("f64" if args.build_precision == "f64" else "f32") + " registers / f32 storage build",
         "data": "synthetic",
         "config": {"workload": "full fit: 2M tracks, 17 barrel layers r=4..100 cm, 0.02 X0/layer + energy loss, "
                                "5% missing hits (6-17 hits), pT U[0.5,10] GeV, |eta|<1, Bz=3.8 T; "
                                "then batched build: 64 events log-uniform [1k,50k] tracks + 20% noise hits, "
                                "64x16 bins, N=6, chi2<30",
                    "tracks": n, "layers": L, "fit_hits": n_hits, "events": bp.n_events, "seeds": n_seeds,
-                   "build_hits": int(bp.hit_pos.shape[0]), "build_mode": args.build_mode},
+                   "build_hits": int(bp.hit_pos.shape[0]), "build_mode": args.build_mode,
+                   "build_precision": args.build_precision, "fit_fp64": bool(args.fit_fp64)},
         "seeds_built_per_s": seeds_per_s,
         "fit_ms": fit_ms, "bin_ms": bin_ms, "build_ms": build_ms,
         "roofline": roof,

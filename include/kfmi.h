@@ -125,6 +125,10 @@ int32_t kf_update(kf_ctx* ctx, int64_t n, int64_t ld, float* state, float* cov, 
  * records are written at row index l-1 + (n_layers-1) * i, unused rows get
  * NaN.  (Learned search window training data.) */
 #define KF_FIT_EMIT_RESIDUALS 1u
+/* KF_FIT_FP64: keep the track in double-precision registers between layers
+ * (HBM stays float32).  Default: float32 registers; updates always compute in
+ * double precision. */
+#define KF_FIT_FP64 2u
 #define KF_RES_FEATURES 8
 typedef struct {
   int64_t n, ld;
@@ -233,6 +237,8 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* args);
 #define KF_BUILD_PERSISTENT 1
 #define KF_WINDOW_PLAIN 0
 #define KF_WINDOW_LEARNED 1
+#define KF_PREC_F32 0
+#define KF_PREC_F64 1
 typedef struct {
   int32_t max_cands;   /* 1..8 */
   float chi2_cut;      /* > 0 */
@@ -242,6 +248,7 @@ typedef struct {
   int32_t window_mode; /* KF_WINDOW_PLAIN or KF_WINDOW_LEARNED */
   int32_t waves_per_block; /* 0 = library choice */
   int32_t blocks_per_cu;   /* persistent mode occupancy, 0 = library choice */
+  int32_t precision;       /* KF_PREC_F32 or KF_PREC_F64: candidate registers (HBM is float32 either way) */
 } kf_build_cfg;
 typedef struct {
   int64_t n_events, n_seeds, ld_seed;

@@ -241,7 +241,7 @@ __device__ __forceinline__ float wrap_pi(float a) {
   return a;
 }
 
-template <int G>
+template <int G, typename T>
 __device__ void build_tile(const BuildP& p, int64_t tile) {
   constexpr int SPW = 64 / G;  // seeds per wave
   const int lane = threadIdx.x & 63;
@@ -261,40 +261,40 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
     }
     ev = lo;
   }
-  const float qf = seed_ok ? static_cast<float>(p.seed_charge[s]) : 1.f;
-  const float a = -qf * kCLight * p.g.bz;
-  float st[6], cv[21];
+  const T a = T(-static_cast<double>(seed_ok ? p.seed_charge[s] : 1) * kCLight * p.g.bz);
+  T st[6], cv[21];
   int32_t status = 0;
   if (seed_ok && slot == 0) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) st[k] = p.seed_state[k * p.ld_seed + s];
+    for (int k = 0; k < 6; ++k) st[k] = T(p.seed_state[k * p.ld_seed + s]);
 #pragma unroll
-    for (int k = 0; k < 21; ++k) cv[k] = p.seed_cov[k * p.ld_seed + s];
+    for (int k = 0; k < 21; ++k) cv[k] = T(p.seed_cov[k * p.ld_seed + s]);
     status = finite6_21(st, cv) ? 0 : ST_NONFINITE;
   } else {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) st[k] = 0.f;
+    for (int k = 0; k < 6; ++k) st[k] = T(0);
 #pragma unroll
-    for (int k = 0; k < 21; ++k) cv[k] = 0.f;
+    for (int k = 0; k < 21; ++k) cv[k] = T(0);
   }
-  float chi2 = 0.f;
+  T chi2 = T(0);
   int nhits = 3;
   int nc = seed_ok ? 1 : 0;  // candidates of this seed (same in all its lanes)
   uint64_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0;
+  const float4* recs = reinterpret_cast<const float4*>(p.binned);
 
   for (int l = p.first_layer; l < L; ++l) {
     const bool active = slot < nc;
     const int64_t el = static_cast<int64_t>(ev) * L + l;
     // ---- propagate (material of the layer the candidate sits on, then the crossing)
-    float ps[6], pc[21];
+    T ps[6], pc[21];
 #pragma unroll
     for (int k = 0; k < 6; ++k) ps[k] = st[k];
 #pragma unroll
     for (int k = 0; k < 21; ++k) pc[k] = cv[k];
     int32_t pstat = status;
     if (active && status == 0) {
-      int32_t r = material(ps, pc, p.g.x_over_x0[l - 1], p.g.eloss_per_x0, p.g.mass);
-      if (!r) r = propagate(ps, pc, a, p.g.r[l], p.g.z_half[l]);
+      int32_t r = material(ps, pc, T(p.g.x_over_x0[l - 1]), T(p.g.eloss_per_x0), T(p.g.mass));
+      if (!r) r = propagate(ps, pc, a, T(p.g.r[l]), T(p.g.z_half[l]));
       if (r) {
         pstat = r;
 #pragma unroll
@@ -305,22 +305,22 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
       n_steps++;
     }
     // ---- scan the window's bins, keep the best N children of this candidate
-    float lkey[G];
+    T lkey[G];
     int32_t lidx[G], lslot[G];
 #pragma unroll
     for (int t = 0; t < G; ++t) {
-      lkey[t] = INFINITY;
+      lkey[t] = T(INFINITY);
       lidx[t] = 0x7FFFFFFF;
       lslot[t] = 0;
     }
     int cnt = 0;
     if (active && pstat == 0) {
       const float R = p.g.r[l];
-      const float irp = __frsqrt_rn(ps[0] * ps[0] + ps[1] * ps[1]);
-      const float tx = -ps[1] * irp, ty = ps[0] * irp;
-      const float ctt = tx * tx * pc[0] + 2.f * tx * ty * pc[1] + ty * ty * pc[2];
-      const float rtt = ctt + p.layer_vmax[2 * el];
-      const float rzz = pc[5] + p.layer_vmax[2 * el + 1];
+      const LocalPred<T> lp = local_pred(ps, pc);
+      const float tx = float(lp.tx), ty = float(lp.ty);
+      const float px0 = float(ps[0]), py0 = float(ps[1]), pz0 = float(ps[2]);
+      const float rtt = float(lp.att) + p.layer_vmax[2 * el];
+      const float rzz = float(pc[5]) + p.layer_vmax[2 * el + 1];
       const float fac = 1.f + p.margin;
       const float wt = sqrtf(p.chi2_cut * rtt) * fac;
       const float wz = sqrtf(p.chi2_cut * rzz) * fac;
@@ -329,17 +329,16 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
       if (sphi < 1.f) {
         const float dphi = asinf(sphi);
         if (dphi < 1.5707963f) {
-          const float php = atan2f(ps[1], ps[0]);
+          const float php = atan2f(py0, px0);
           ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
           const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
           nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
         }
       }
       const float emax = asinhf(p.g.z_half[l] / R);
-      const int ie0 = eta_bin_f(ps[2] - wz, R, emax, p.n_eta);
-      const int ie1 = eta_bin_f(ps[2] + wz, R, emax, p.n_eta);
+      const int ie0 = eta_bin_f(pz0 - wz, R, emax, p.n_eta);
+      const int ie1 = eta_bin_f(pz0 + wz, R, emax, p.n_eta);
       const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
-      const float4* recs = reinterpret_cast<const float4*>(p.binned);
       for (int ie = ie0; ie <= ie1; ++ie) {
         const int row = ie * p.n_phi;
         const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
@@ -356,25 +355,25 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
           }
           for (int j = j0; j < j1; ++j) {
             const float4 h = recs[static_cast<int64_t>(j) * 3];
-            const float dx = h.x - ps[0], dy = h.y - ps[1], dz = h.z - ps[2];
+            const float dx = h.x - px0, dy = h.y - py0, dz = h.z - pz0;
             n_box++;
             if (fabsf(tx * dx + ty * dy) > wt || fabsf(dz) > wz) continue;
             const float4 c0 = recs[static_cast<int64_t>(j) * 3 + 1];
             const float4 c1 = recs[static_cast<int64_t>(j) * 3 + 2];
             const float m[3] = {h.x, h.y, h.z};
             const float v[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
-            float ri[6], rr[3], c2;
+            T c2;
             n_chi2++;
-            if (chi2_of(ps, pc, m, v, ri, rr, c2)) continue;
-            if (!(c2 < p.chi2_cut)) continue;
+            if (chi2_on_layer(ps, lp, m, v, c2)) continue;
+            if (!(c2 < T(p.chi2_cut))) continue;
             n_comp++;
-            float nk = chi2 + fmaxf(c2, 0.f);
+            T nk = chi2 + (c2 > T(0) ? c2 : T(0));
             int32_t ni = __float_as_int(h.w);
             int32_t nj = j;
 #pragma unroll
             for (int t = 0; t < G; ++t) {
               const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
-              const float tk = lkey[t];
+              const T tk = lkey[t];
               const int32_t ti = lidx[t], tj = lslot[t];
               lkey[t] = sw ? nk : tk;
               lidx[t] = sw ? ni : ti;
@@ -392,22 +391,25 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
     bool hole_left = active;
     uint64_t mine = ~0ull;  // the child that becomes this slot's candidate
     int32_t mine_slot = -1;
+    T mine_chi2 = T(0);
     int new_nc = 0;
     for (int r = 0; r < N; ++r) {
       uint64_t k = ~0ull;
       const bool has_hit = active && pstat == 0 && cnt > 0;
       if (has_hit)
-        k = make_key(nhits + 1, lkey[0], slot, static_cast<uint32_t>(lidx[0]));
+        k = make_key(nhits + 1, float(lkey[0]), slot, static_cast<uint32_t>(lidx[0]));
       else if (hole_left)
-        k = make_key(nhits, chi2, slot, kHole);
+        k = make_key(nhits, float(chi2), slot, kHole);
       const uint64_t kmin = group_min<G>(k);
       const int winner = gbase + key_parent(kmin);
       const int32_t wslot = __shfl(has_hit ? lslot[0] : -1, winner);
+      const T wchi2 = __shfl(has_hit ? lkey[0] : chi2, winner);
       if (kmin != ~0ull) {
         new_nc = r + 1;
         if (slot == r) {
           mine = kmin;
           mine_slot = wslot;
+          mine_chi2 = wchi2;
         }
         if (k == kmin) {
           if (has_hit) {
@@ -417,7 +419,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
               lidx[t] = lidx[t + 1];
               lslot[t] = lslot[t + 1];
             }
-            lkey[G - 1] = INFINITY;
+            lkey[G - 1] = T(INFINITY);
             cnt--;
           } else {
             hole_left = false;
@@ -434,17 +436,16 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
     status = __shfl(pstat, src);
     if (mine != ~0ull) {
       nhits = key_nhits(mine);
-      chi2 = key_chi2(mine);
+      chi2 = mine_chi2;
       const uint32_t hid = key_hit(mine);
       if (hid != kHole && status == 0) {
-        const float4* recs = reinterpret_cast<const float4*>(p.binned);
         const float4 h = recs[static_cast<int64_t>(mine_slot) * 3];
         const float4 c0 = recs[static_cast<int64_t>(mine_slot) * 3 + 1];
         const float4 c1 = recs[static_cast<int64_t>(mine_slot) * 3 + 2];
         const float m[3] = {h.x, h.y, h.z};
         const float v[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
-        float dc2;
-        const int32_t r = update(st, cv, m, v, dc2);
+        T dc2;
+        const int32_t r = update_on_layer<T, double>(st, cv, m, v, dc2);
         if (r) status = r;
         n_upd++;
       }
@@ -458,15 +459,15 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
     if (slot == 0) p.n_cands[s] = nc;
     if (slot < N) {
       const bool live = slot < nc;
-      p.cand_chi2[s * N + slot] = live ? chi2 : 0.f;
+      p.cand_chi2[s * N + slot] = live ? static_cast<float>(chi2) : 0.f;
       p.cand_nhits[s * N + slot] = live ? nhits : 0;
       p.cand_status[s * N + slot] = live ? status : 0;
     }
     if (slot == 0 && p.best_state) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) p.best_state[k * p.ld_seed + s] = st[k];
+      for (int k = 0; k < 6; ++k) p.best_state[k * p.ld_seed + s] = static_cast<float>(st[k]);
 #pragma unroll
-      for (int k = 0; k < 21; ++k) p.best_cov[k * p.ld_seed + s] = cv[k];
+      for (int k = 0; k < 21; ++k) p.best_cov[k * p.ld_seed + s] = static_cast<float>(cv[k]);
     }
   }
   // backtrack the parent chain in place: at each layer every lane reads its
@@ -504,13 +505,13 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
   }
 }
 
-template <int G>
+template <int G, typename T>
 __global__ void __launch_bounds__(256) build_tiled_kernel(BuildP p) {
   const int64_t tile = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  build_tile<G>(p, tile);
+  build_tile<G, T>(p, tile);
 }
 
-template <int G>
+template <int G, typename T>
 __global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t n_tiles) {
   const int lane = threadIdx.x & 63;
   for (;;) {
@@ -518,7 +519,7 @@ __global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t
     if (lane == 0) t = atomicAdd(p.queue, 1);
     t = __shfl(t, 0);
     if (t >= n_tiles) break;
-    build_tile<G>(p, t);
+    build_tile<G, T>(p, t);
   }
 }
 
@@ -579,6 +580,8 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   if (cfg->mode != KF_BUILD_TILED && cfg->mode != KF_BUILD_PERSISTENT)
     return set_error(KF_ERR_INVALID_ARG, "unknown mode %d", cfg->mode);
   if (cfg->window_mode != KF_WINDOW_PLAIN) return set_error(KF_ERR_INVALID_ARG, "window mode not available");
+  if (cfg->precision != KF_PREC_F32 && cfg->precision != KF_PREC_F64)
+    return set_error(KF_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
   if (a->n_events < 0 || a->n_seeds < 0 || a->ld_seed < a->n_seeds)
     return set_error(KF_ERR_INVALID_ARG, "bad sizes");
   if (a->first_layer < 3 || a->first_layer > L) return set_error(KF_ERR_INVALID_ARG, "first_layer must be in [3, L]");
@@ -627,14 +630,19 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   const int wpb = cfg->waves_per_block > 0 ? cfg->waves_per_block : 4;
   if (wpb > 4) return set_error(KF_ERR_INVALID_ARG, "waves_per_block must be 1..4");
   hipStream_t stream = kfh::stream_of(a->stream);
+  const bool f64 = cfg->precision == KF_PREC_F64;
   if (cfg->mode == KF_BUILD_TILED) {
     const unsigned grid = static_cast<unsigned>((n_tiles + wpb - 1) / wpb);
     const unsigned block = 64u * wpb;
-    switch (G) {
-      case 1: build_tiled_kernel<1><<<grid, block, 0, stream>>>(p); break;
-      case 2: build_tiled_kernel<2><<<grid, block, 0, stream>>>(p); break;
-      case 4: build_tiled_kernel<4><<<grid, block, 0, stream>>>(p); break;
-      default: build_tiled_kernel<8><<<grid, block, 0, stream>>>(p); break;
+    switch (G * 2 + (f64 ? 1 : 0)) {
+      case 2: build_tiled_kernel<1, float><<<grid, block, 0, stream>>>(p); break;
+      case 3: build_tiled_kernel<1, double><<<grid, block, 0, stream>>>(p); break;
+      case 4: build_tiled_kernel<2, float><<<grid, block, 0, stream>>>(p); break;
+      case 5: build_tiled_kernel<2, double><<<grid, block, 0, stream>>>(p); break;
+      case 8: build_tiled_kernel<4, float><<<grid, block, 0, stream>>>(p); break;
+      case 9: build_tiled_kernel<4, double><<<grid, block, 0, stream>>>(p); break;
+      case 16: build_tiled_kernel<8, float><<<grid, block, 0, stream>>>(p); break;
+      default: build_tiled_kernel<8, double><<<grid, block, 0, stream>>>(p); break;
     }
     return kfh::check_hip(hipGetLastError(), "build_tiled_kernel launch");
   }
@@ -645,11 +653,15 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   const int bpc = cfg->blocks_per_cu > 0 ? cfg->blocks_per_cu : 2;
   const unsigned grid = static_cast<unsigned>(ctx->num_cus * bpc);
   const unsigned block = 64u * wpb;
-  switch (G) {
-    case 1: build_persistent_kernel<1><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    case 2: build_persistent_kernel<2><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    case 4: build_persistent_kernel<4><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    default: build_persistent_kernel<8><<<grid, block, 0, stream>>>(p, n_tiles); break;
+  switch (G * 2 + (f64 ? 1 : 0)) {
+    case 2: build_persistent_kernel<1, float><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    case 3: build_persistent_kernel<1, double><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    case 4: build_persistent_kernel<2, float><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    case 5: build_persistent_kernel<2, double><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    case 8: build_persistent_kernel<4, float><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    case 9: build_persistent_kernel<4, double><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    case 16: build_persistent_kernel<8, float><<<grid, block, 0, stream>>>(p, n_tiles); break;
+    default: build_persistent_kernel<8, double><<<grid, block, 0, stream>>>(p, n_tiles); break;
   }
   return kfh::check_hip(hipGetLastError(), "build_persistent_kernel launch");
 }

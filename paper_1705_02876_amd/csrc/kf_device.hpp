@@ -1,8 +1,11 @@
-// kf_device.hpp -- register-resident FP32 Kalman-filter arithmetic for gfx950.
+// kf_device.hpp -- register-resident Kalman-filter arithmetic for gfx950.
 //
 // One track per lane.  State s[6] = (x, y, z, px, py, pz); covariance c[21]
 // packed lower triangle, k = i(i+1)/2 + j.  Everything stays in VGPRs: all
-// index expressions below are compile-time constants after unrolling.
+// index expressions below are compile-time constants after unrolling.  HBM
+// always holds float32; the register type T of a kernel is float or double
+// (gfx950 issues FP64 FMA at the rate of unpacked FP32 FMA), and Kalman
+// updates compute in U = double in both cases.
 //
 // Helix propagation (the paper's core KF step, Sec. 2.1 / Sec. 3): with
 // a = -q c bz and kappa = a / pT the transverse direction turns by
@@ -11,9 +14,9 @@
 //     A w^2 + 2 au w - D / 2 = 0,  A = 2 (1 + kappa an) - kappa^2 D / 2,
 // with au = P0.u, an = P0.n, D = R^2 - |P0|^2 (u = direction, n = left normal).
 // Its smallest positive root gives the first crossing within half a turn with
-// no 1/kappa or rho^2 terms, so stiff tracks keep full FP32 precision; sin and
-// cos of phi follow from tau algebraically and only t = 2 atan(tau) / kappa
-// needs a transcendental.
+// no 1/kappa or rho^2 terms, so stiff tracks keep full precision; sin and cos
+// of phi follow from tau algebraically and only t = 2 atan(tau) / kappa needs
+// a transcendental.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,7 +26,7 @@
 
 namespace kfd {
 
-constexpr float kCLight = 0.299792458e-2f;  // GeV / (T cm)
+constexpr double kCLight = 0.299792458e-2;  // GeV / (T cm)
 constexpr int kMaxLayers = 32;
 
 enum : int32_t { ST_NO_CROSSING = 1, ST_OUT_OF_Z = 2, ST_NONFINITE = 4, ST_NOT_PD = 8, ST_STOPPED = 16 };
@@ -40,64 +43,82 @@ struct Geom {
 
 constexpr int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
-KF_DEV bool finite6_21(const float s[6], const float c[21]) {
-  float acc = 0.f;
+// precision-generic math
+KF_DEV float rsqrt_t(float x) { return __frsqrt_rn(x); }
+KF_DEV double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+KF_DEV float atan_t(float x) { return atanf(x); }
+KF_DEV double atan_t(double x) { return atan(x); }
+KF_DEV float log_t(float x) { return logf(x); }
+KF_DEV double log_t(double x) { return log(x); }
+KF_DEV float sqrt_t(float x) { return sqrtf(x); }
+KF_DEV double sqrt_t(double x) { return sqrt(x); }
+KF_DEV float abs_t(float x) { return fabsf(x); }
+KF_DEV double abs_t(double x) { return fabs(x); }
+KF_DEV float copysign_t(float a, float b) { return copysignf(a, b); }
+KF_DEV double copysign_t(double a, double b) { return copysign(a, b); }
+
+template <typename T>
+KF_DEV bool finite6_21(const T s[6], const T c[21]) {
+  T acc = T(0);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) acc += s[i] * 0.f;
+  for (int i = 0; i < 6; ++i) acc += s[i] * T(0);
 #pragma unroll
-  for (int i = 0; i < 21; ++i) acc += c[i] * 0.f;
-  return acc == 0.f;  // any Inf/NaN turns the sum into NaN
+  for (int i = 0; i < 21; ++i) acc += c[i] * T(0);
+  return acc == T(0);  // any Inf/NaN turns the sum into NaN
 }
 
 // Result of a propagation: the Jacobian in its sparse form (23 non-zeros) and
 // the new state.  Rows x, y, px, py have non-zeros in columns (x, y, px, py);
 // row z in all six columns (with J[z][z] = 1); row pz is e_pz.
+template <typename T>
 struct Prop {
-  float s[6];
-  float jx[4], jy[4], jpx[4], jpy[4];  // columns (x, y, px, py)
-  float jz[6];                         // columns (x, y, z, px, py, pz)
-  float t;                             // transverse path length
+  T s[6];
+  T jx[4], jy[4], jpx[4], jpy[4];  // columns (x, y, px, py)
+  T jz[6];                         // columns (x, y, z, px, py, pz)
+  T t;                             // transverse path length
 };
 
 // Helix crossing of radius R.  Returns status bits (0 on success).
-KF_DEV int32_t helix_to_r(const float s[6], float a, float R, float zh, Prop& o) {
-  const float x = s[0], y = s[1], z = s[2], px = s[3], py = s[4], pz = s[5];
-  const float pt2 = px * px + py * py;
-  const float ipt = __frsqrt_rn(pt2);
-  const float ux = px * ipt, uy = py * ipt;
-  const float au = x * ux + y * uy;
-  const float an = y * ux - x * uy;
-  const float D = R * R - (x * x + y * y);
-  const float kap = a * ipt;
-  const float A = 2.f * (1.f + kap * an) - 0.5f * kap * kap * D;
-  const float disc = au * au + 0.5f * A * D;
-  if (!(disc >= 0.f)) return ST_NO_CROSSING;
-  const float sq = sqrtf(disc);
+template <typename T>
+KF_DEV int32_t helix_to_r(const T s[6], T a, T R, T zh, Prop<T>& o) {
+  const T x = s[0], y = s[1], z = s[2], px = s[3], py = s[4], pz = s[5];
+  const T pt2 = px * px + py * py;
+  const T ipt = rsqrt_t(pt2);
+  const T ux = px * ipt, uy = py * ipt;
+  const T au = x * ux + y * uy;
+  const T an = y * ux - x * uy;
+  const T D = R * R - (x * x + y * y);
+  const T kap = a * ipt;
+  const T A = T(2) * (T(1) + kap * an) - T(0.5) * kap * kap * D;
+  const T disc = au * au + T(0.5) * A * D;
+  if (!(disc >= T(0))) return ST_NO_CROSSING;
+  const T sq = sqrt_t(disc);
   // numerically stable roots of A w^2 + 2 au w - D/2 = 0
-  const float qq = -(au + copysignf(sq, au));
-  const float r1 = qq / A;
-  const float r2 = (-0.5f * D) / qq;
-  float w = INFINITY;
-  if (r1 > 0.f) w = r1;
-  if (r2 > 0.f && r2 < w) w = r2;
-  if (!(w < INFINITY)) return ST_NO_CROSSING;
-  const float tau = kap * w;
-  const float tau2 = tau * tau;
+  const T qq = -(au + copysign_t(sq, au));
+  const T r1 = qq / A;
+  const T r2 = (T(-0.5) * D) / qq;
+  T w = T(INFINITY);
+  if (r1 > T(0)) w = r1;
+  if (r2 > T(0) && r2 < w) w = r2;
+  if (!(w < T(INFINITY))) return ST_NO_CROSSING;
+  const T tau = kap * w;
+  const T tau2 = tau * tau;
   // atan(tau) / tau, series near 0
-  float at_over = (fabsf(tau) < 1e-3f) ? (1.f - tau2 * (1.f / 3.f)) : (atanf(tau) / tau);
-  const float t = 2.f * w * at_over;
-  const float phi = kap * t;
-  const float iden = 1.f / (1.f + tau2);
-  const float sn = 2.f * tau * iden;
-  const float cs = (1.f - tau2) * iden;
-  const float S = 2.f * w * iden;         // sin(phi) / kappa
-  const float Cc = 2.f * tau * w * iden;  // (1 - cos(phi)) / kappa
-  const float xn = x + S * ux - Cc * uy;
-  const float yn = y + S * uy + Cc * ux;
-  const float zn = z + pz * ipt * t;
-  if (zh > 0.f && fabsf(zn) > zh) return ST_OUT_OF_Z;
-  const float pxn = px * cs - py * sn;
-  const float pyn = py * cs + px * sn;
+  const T small = sizeof(T) == 4 ? T(1e-3) : T(1e-5);
+  const T at_over = (abs_t(tau) < small) ? (T(1) - tau2 * (T(1) / T(3)) + tau2 * tau2 * T(0.2)) : (atan_t(tau) / tau);
+  const T t = T(2) * w * at_over;
+  const T phi = kap * t;
+  const T iden = T(1) / (T(1) + tau2);
+  const T sn = T(2) * tau * iden;
+  const T cs = (T(1) - tau2) * iden;
+  const T S = T(2) * w * iden;         // sin(phi) / kappa
+  const T Cc = T(2) * tau * w * iden;  // (1 - cos(phi)) / kappa
+  const T xn = x + S * ux - Cc * uy;
+  const T yn = y + S * uy + Cc * ux;
+  const T zn = z + pz * ipt * t;
+  if (zh > T(0) && abs_t(zn) > zh) return ST_OUT_OF_Z;
+  const T pxn = px * cs - py * sn;
+  const T pyn = py * cs + px * sn;
   o.s[0] = xn;
   o.s[1] = yn;
   o.s[2] = zn;
@@ -106,33 +127,33 @@ KF_DEV int32_t helix_to_r(const float s[6], float a, float R, float zh, Prop& o)
   o.s[5] = pz;
   o.t = t;
   // fixed-t Jacobian entries (sin(phi)/a = S/pT, (1-cos(phi))/a = Cc/pT)
-  const float ipt2 = ipt * ipt;
-  const float tp3 = t * ipt2 * ipt;  // t / pT^3
-  const float fp2 = phi * ipt2;      // phi / pT^2
-  const float Sp = S * ipt, Cp = Cc * ipt;
-  const float a03 = Sp - pxn * px * tp3;
-  const float a04 = -Cp - pxn * py * tp3;
-  const float a13 = Cp - pyn * px * tp3;
-  const float a14 = Sp - pyn * py * tp3;
-  const float a23 = -pz * px * tp3;
-  const float a24 = -pz * py * tp3;
-  const float a25 = t * ipt;
-  const float a33 = cs + pyn * px * fp2;
-  const float a34 = -sn + pyn * py * fp2;
-  const float a43 = sn - pxn * px * fp2;
-  const float a44 = cs - pxn * py * fp2;
+  const T ipt2 = ipt * ipt;
+  const T tp3 = t * ipt2 * ipt;  // t / pT^3
+  const T fp2 = phi * ipt2;      // phi / pT^2
+  const T Sp = S * ipt, Cp = Cc * ipt;
+  const T a03 = Sp - pxn * px * tp3;
+  const T a04 = -Cp - pxn * py * tp3;
+  const T a13 = Cp - pyn * px * tp3;
+  const T a14 = Sp - pyn * py * tp3;
+  const T a23 = -pz * px * tp3;
+  const T a24 = -pz * py * tp3;
+  const T a25 = t * ipt;
+  const T a33 = cs + pyn * px * fp2;
+  const T a34 = -sn + pyn * py * fp2;
+  const T a43 = sn - pxn * px * fp2;
+  const T a44 = cs - pxn * py * fp2;
   // surface constraint: J = (I - v w^T) Jt
-  const float v0 = pxn * ipt, v1 = pyn * ipt, v2 = pz * ipt, v3 = -kap * pyn, v4 = kap * pxn;
-  const float iden2 = 1.f / (xn * v0 + yn * v1);
-  const float w0 = xn * iden2, w1 = yn * iden2;
-  const float w3 = w0 * a03 + w1 * a13;
-  const float w4 = w0 * a04 + w1 * a14;
-  o.jx[0] = 1.f - v0 * w0;
+  const T v0 = pxn * ipt, v1 = pyn * ipt, v2 = pz * ipt, v3 = -kap * pyn, v4 = kap * pxn;
+  const T iden2 = T(1) / (xn * v0 + yn * v1);
+  const T w0 = xn * iden2, w1 = yn * iden2;
+  const T w3 = w0 * a03 + w1 * a13;
+  const T w4 = w0 * a04 + w1 * a14;
+  o.jx[0] = T(1) - v0 * w0;
   o.jx[1] = -v0 * w1;
   o.jx[2] = a03 - v0 * w3;
   o.jx[3] = a04 - v0 * w4;
   o.jy[0] = -v1 * w0;
-  o.jy[1] = 1.f - v1 * w1;
+  o.jy[1] = T(1) - v1 * w1;
   o.jy[2] = a13 - v1 * w3;
   o.jy[3] = a14 - v1 * w4;
   o.jpx[0] = -v3 * w0;
@@ -145,7 +166,7 @@ KF_DEV int32_t helix_to_r(const float s[6], float a, float R, float zh, Prop& o)
   o.jpy[3] = a44 - v4 * w4;
   o.jz[0] = -v2 * w0;
   o.jz[1] = -v2 * w1;
-  o.jz[2] = 1.f;
+  o.jz[2] = T(1);
   o.jz[3] = a23 - v2 * w3;
   o.jz[4] = a24 - v2 * w4;
   o.jz[5] = a25;
@@ -153,40 +174,42 @@ KF_DEV int32_t helix_to_r(const float s[6], float a, float R, float zh, Prop& o)
 }
 
 // c <- J c J^T using the 23-non-zero structure.  132 + 89 FMA.
-KF_DEV void transport(float c[21], const Prop& p) {
-  float T[6][6];
+template <typename T>
+KF_DEV void transport(T c[21], const Prop<T>& p) {
+  T M[6][6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    const float c0 = c[tri(0, k)], c1 = c[tri(1, k)], c2 = c[tri(2, k)];
-    const float c3 = c[tri(3, k)], c4 = c[tri(4, k)], c5 = c[tri(5, k)];
-    T[0][k] = p.jx[0] * c0 + p.jx[1] * c1 + p.jx[2] * c3 + p.jx[3] * c4;
-    T[1][k] = p.jy[0] * c0 + p.jy[1] * c1 + p.jy[2] * c3 + p.jy[3] * c4;
-    T[2][k] = p.jz[0] * c0 + p.jz[1] * c1 + c2 + p.jz[3] * c3 + p.jz[4] * c4 + p.jz[5] * c5;
-    T[3][k] = p.jpx[0] * c0 + p.jpx[1] * c1 + p.jpx[2] * c3 + p.jpx[3] * c4;
-    T[4][k] = p.jpy[0] * c0 + p.jpy[1] * c1 + p.jpy[2] * c3 + p.jpy[3] * c4;
-    T[5][k] = c5;
+    const T c0 = c[tri(0, k)], c1 = c[tri(1, k)], c2 = c[tri(2, k)];
+    const T c3 = c[tri(3, k)], c4 = c[tri(4, k)], c5 = c[tri(5, k)];
+    M[0][k] = p.jx[0] * c0 + p.jx[1] * c1 + p.jx[2] * c3 + p.jx[3] * c4;
+    M[1][k] = p.jy[0] * c0 + p.jy[1] * c1 + p.jy[2] * c3 + p.jy[3] * c4;
+    M[2][k] = p.jz[0] * c0 + p.jz[1] * c1 + c2 + p.jz[3] * c3 + p.jz[4] * c4 + p.jz[5] * c5;
+    M[3][k] = p.jpx[0] * c0 + p.jpx[1] * c1 + p.jpx[2] * c3 + p.jpx[3] * c4;
+    M[4][k] = p.jpy[0] * c0 + p.jpy[1] * c1 + p.jpy[2] * c3 + p.jpy[3] * c4;
+    M[5][k] = c5;
   }
-  // C'[i][l] = sum_k T[i][k] J[l][k], l <= i
+  // C'[i][l] = sum_k M[i][k] J[l][k], l <= i
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const float* Ti = T[i];
-    c[tri(i, 0)] = p.jx[0] * Ti[0] + p.jx[1] * Ti[1] + p.jx[2] * Ti[3] + p.jx[3] * Ti[4];
-    if (i >= 1) c[tri(i, 1)] = p.jy[0] * Ti[0] + p.jy[1] * Ti[1] + p.jy[2] * Ti[3] + p.jy[3] * Ti[4];
+    const T* Mi = M[i];
+    c[tri(i, 0)] = p.jx[0] * Mi[0] + p.jx[1] * Mi[1] + p.jx[2] * Mi[3] + p.jx[3] * Mi[4];
+    if (i >= 1) c[tri(i, 1)] = p.jy[0] * Mi[0] + p.jy[1] * Mi[1] + p.jy[2] * Mi[3] + p.jy[3] * Mi[4];
     if (i >= 2)
-      c[tri(i, 2)] = p.jz[0] * Ti[0] + p.jz[1] * Ti[1] + Ti[2] + p.jz[3] * Ti[3] + p.jz[4] * Ti[4] + p.jz[5] * Ti[5];
-    if (i >= 3) c[tri(i, 3)] = p.jpx[0] * Ti[0] + p.jpx[1] * Ti[1] + p.jpx[2] * Ti[3] + p.jpx[3] * Ti[4];
-    if (i >= 4) c[tri(i, 4)] = p.jpy[0] * Ti[0] + p.jpy[1] * Ti[1] + p.jpy[2] * Ti[3] + p.jpy[3] * Ti[4];
-    if (i >= 5) c[tri(i, 5)] = Ti[5];
+      c[tri(i, 2)] = p.jz[0] * Mi[0] + p.jz[1] * Mi[1] + Mi[2] + p.jz[3] * Mi[3] + p.jz[4] * Mi[4] + p.jz[5] * Mi[5];
+    if (i >= 3) c[tri(i, 3)] = p.jpx[0] * Mi[0] + p.jpx[1] * Mi[1] + p.jpx[2] * Mi[3] + p.jpx[3] * Mi[4];
+    if (i >= 4) c[tri(i, 4)] = p.jpy[0] * Mi[0] + p.jpy[1] * Mi[1] + p.jpy[2] * Mi[3] + p.jpy[3] * Mi[4];
+    if (i >= 5) c[tri(i, 5)] = Mi[5];
   }
 }
 
 // Propagate + transport in place; on failure s and c are left unchanged.
-KF_DEV int32_t propagate(float s[6], float c[21], float a, float R, float zh) {
+template <typename T>
+KF_DEV int32_t propagate(T s[6], T c[21], T a, T R, T zh) {
   if (!finite6_21(s, c)) return ST_NONFINITE;
-  Prop p;
+  Prop<T> p;
   int32_t st = helix_to_r(s, a, R, zh, p);
   if (st) return st;
-  float cn[21];
+  T cn[21];
 #pragma unroll
   for (int k = 0; k < 21; ++k) cn[k] = c[k];
   transport(cn, p);
@@ -200,23 +223,24 @@ KF_DEV int32_t propagate(float s[6], float c[21], float a, float R, float zh) {
 
 // Thin scatterer (multiple scattering, Highland width, and mean energy loss)
 // for a track sitting on a layer of normal thickness xx0 radiation lengths.
-KF_DEV int32_t material(float s[6], float c[21], float xx0, float eloss, float mass) {
-  if (!(xx0 > 0.f)) return 0;
-  const float p2 = s[3] * s[3] + s[4] * s[4] + s[5] * s[5];
-  const float ip = __frsqrt_rn(p2);
-  const float p = p2 * ip;
-  const float u0 = s[3] * ip, u1 = s[4] * ip, u2 = s[5] * ip;
-  const float ir = __frsqrt_rn(s[0] * s[0] + s[1] * s[1]);
-  const float cospsi = fabsf((u0 * s[0] + u1 * s[1]) * ir);
-  const float tt = xx0 / cospsi;
-  const float m2 = mass * mass;
-  const float E = sqrtf(p2 + m2);
-  const float beta = p / E;
-  const float th0 = 0.0136f / (beta * p) * sqrtf(tt) * (1.f + 0.038f * logf(tt / (beta * beta)));
-  const float E2 = E - eloss * tt;
+template <typename T>
+KF_DEV int32_t material(T s[6], T c[21], T xx0, T eloss, T mass) {
+  if (!(xx0 > T(0))) return 0;
+  const T p2 = s[3] * s[3] + s[4] * s[4] + s[5] * s[5];
+  const T ip = rsqrt_t(p2);
+  const T p = p2 * ip;
+  const T u0 = s[3] * ip, u1 = s[4] * ip, u2 = s[5] * ip;
+  const T ir = rsqrt_t(s[0] * s[0] + s[1] * s[1]);
+  const T cospsi = abs_t((u0 * s[0] + u1 * s[1]) * ir);
+  const T tt = xx0 / cospsi;
+  const T m2 = mass * mass;
+  const T E = sqrt_t(p2 + m2);
+  const T beta = p / E;
+  const T th0 = T(0.0136) / (beta * p) * sqrt_t(tt) * (T(1) + T(0.038) * log_t(tt / (beta * beta)));
+  const T E2 = E - eloss * tt;
   if (!(E2 > mass)) return ST_STOPPED;
-  const float pn = sqrtf((E2 - mass) * (E2 + mass));
-  const float f = pn / p;
+  const T pn = sqrt_t((E2 - mass) * (E2 + mass));
+  const T f = pn / p;
 #pragma unroll
   for (int i = 3; i < 6; ++i) s[i] *= f;
 #pragma unroll
@@ -226,120 +250,236 @@ KF_DEV int32_t material(float s[6], float c[21], float xx0, float eloss, float m
 #pragma unroll
     for (int j = 3; j <= i; ++j) c[tri(i, j)] *= f * f;
   }
-  const float k = pn * pn * th0 * th0;
-  const float u[3] = {u0, u1, u2};
+  const T k = pn * pn * th0 * th0;
+  const T u[3] = {u0, u1, u2};
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j) c[tri(i + 3, j + 3)] += k * ((i == j ? 1.f : 0.f) - u[i] * u[j]);
+    for (int j = 0; j <= i; ++j) c[tri(i + 3, j + 3)] += k * ((i == j ? T(1) : T(0)) - u[i] * u[j]);
   return 0;
 }
 
-// Residual covariance R = C_pos + V, its inverse (symmetric, packed 6) and
-// chi2 of the residual r = m - x.  Returns ST_NOT_PD if R is not positive
-// definite (leading minors).
-KF_DEV int32_t chi2_of(const float s[6], const float c[21], const float m[3], const float v[6], float ri[6],
-                       float r[3], float& chi2) {
-  const float a = c[0] + v[0], b = c[1] + v[1], d = c[2] + v[2];
-  const float e = c[3] + v[3], f = c[4] + v[4], g = c[5] + v[5];
-  // R = [[a, b, e], [b, d, f], [e, f, g]]
-  const float i00 = d * g - f * f;
-  const float i10 = e * f - b * g;
-  const float i20 = b * f - d * e;
-  const float det = a * i00 + b * i10 + e * i20;
-  const float m2 = a * d - b * b;
-  if (!(a > 0.f) || !(m2 > 0.f) || !(det > 0.f)) return ST_NOT_PD;
-  const float id = 1.f / det;
+// Inverse of a symmetric 3x3 given by its packed entries (00, 10, 11, 20, 21,
+// 22), by cofactors; returns false unless positive definite (leading minors).
+template <typename T>
+KF_DEV bool inv3_packed(const T r[6], T ri[6]) {
+  const T a = r[0], b = r[1], d = r[2], e = r[3], f = r[4], g = r[5];
+  const T i00 = d * g - f * f;
+  const T i10 = e * f - b * g;
+  const T i20 = b * f - d * e;
+  const T det = a * i00 + b * i10 + e * i20;
+  const T m2 = a * d - b * b;
+  if (!(a > T(0)) || !(m2 > T(0)) || !(det > T(0))) return false;
+  const T id = T(1) / det;
   ri[0] = i00 * id;
   ri[1] = i10 * id;
   ri[2] = (a * g - e * e) * id;
   ri[3] = i20 * id;
   ri[4] = (b * e - a * f) * id;
   ri[5] = m2 * id;
-  r[0] = m[0] - s[0];
-  r[1] = m[1] - s[1];
-  r[2] = m[2] - s[2];
-  const float q0 = ri[0] * r[0] + ri[1] * r[1] + ri[3] * r[2];
-  const float q1 = ri[1] * r[0] + ri[2] * r[1] + ri[4] * r[2];
-  const float q2 = ri[3] * r[0] + ri[4] * r[1] + ri[5] * r[2];
-  chi2 = r[0] * q0 + r[1] * q1 + r[2] * q2;
-  return 0;
+  return true;
 }
 
-// Kalman update with the hit (m, v), computed in precision T (the state and
-// covariance stay float32 in registers and HBM).  The covariance uses the
-// algebraically identical forms C_pos'' = A R^-1 V, C_mom,pos'' = B R^-1 V and
-// C_mom'' = D - B R^-1 B^T (A, B, D = position, cross and momentum blocks),
-// which avoid the cancellation of A - A R^-1 A when the prior is vague.  The
-// remaining cancellation in D - B R^-1 B^T and the 3x3 inverse are what limit
-// a float32 update; gfx950 runs FP64 FMA at the unpacked FP32 rate, so the fit
-// and the build's survivor update use T = double.
-template <typename T>
-KF_DEV int32_t update_t(float s[6], float c[21], const float m[3], const float v[6], float& chi2_out) {
-  const T a = T(c[0]) + T(v[0]), b = T(c[1]) + T(v[1]), d = T(c[2]) + T(v[2]);
-  const T e = T(c[3]) + T(v[3]), f = T(c[4]) + T(v[4]), g = T(c[5]) + T(v[5]);
-  const T i00 = d * g - f * f;
-  const T i10 = e * f - b * g;
-  const T i20 = b * f - d * e;
-  const T det = a * i00 + b * i10 + e * i20;
-  const T m2 = a * d - b * b;
-  if (!(a > T(0)) || !(m2 > T(0)) || !(det > T(0))) return ST_NOT_PD;
-  const T id = T(1) / det;
-  const T Ri[3][3] = {{i00 * id, i10 * id, i20 * id},
-                      {i10 * id, (a * g - e * e) * id, (b * e - a * f) * id},
-                      {i20 * id, (b * e - a * f) * id, m2 * id}};
-  const T r[3] = {T(m[0]) - T(s[0]), T(m[1]) - T(s[1]), T(m[2]) - T(s[2])};
-  T q[3];
+// General Kalman update with the hit (m, v) in global coordinates, computed in
+// precision U: r = m - H x, R = H C H^T + V, chi2 = r^T R^-1 r and, with
+// A, B, D the position, cross and momentum blocks of C, the algebraically
+// identical stable forms C_pos'' = A R^-1 V, C_mom,pos'' = B R^-1 V,
+// C_mom'' = D - B R^-1 B^T of C - K H C (no A - A R^-1 A cancellation under
+// vague priors).  Makes no assumption on C.
+template <typename T, typename U>
+KF_DEV int32_t update_global(T s[6], T c[21], const float m[3], const float v[6], T& chi2_out) {
+  const U rr[6] = {U(c[0]) + U(v[0]), U(c[1]) + U(v[1]), U(c[2]) + U(v[2]),
+                   U(c[3]) + U(v[3]), U(c[4]) + U(v[4]), U(c[5]) + U(v[5])};
+  U ri[6];
+  if (!inv3_packed<U>(rr, ri)) return ST_NOT_PD;
+  const U Ri[3][3] = {{ri[0], ri[1], ri[3]}, {ri[1], ri[2], ri[4]}, {ri[3], ri[4], ri[5]}};
+  const U r[3] = {U(m[0]) - U(s[0]), U(m[1]) - U(s[1]), U(m[2]) - U(s[2])};
+  U q[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) q[i] = Ri[i][0] * r[0] + Ri[i][1] * r[1] + Ri[i][2] * r[2];
-  const T chi2 = r[0] * q[0] + r[1] * q[1] + r[2] * q[2];
-  const T V[3][3] = {{T(v[0]), T(v[1]), T(v[3])}, {T(v[1]), T(v[2]), T(v[4])}, {T(v[3]), T(v[4]), T(v[5])}};
-  T M[3][3];  // R^-1 V
+  const U chi2 = r[0] * q[0] + r[1] * q[1] + r[2] * q[2];
+  const U V[3][3] = {{U(v[0]), U(v[1]), U(v[3])}, {U(v[1]), U(v[2]), U(v[4])}, {U(v[3]), U(v[4]), U(v[5])}};
+  U M[3][3];  // R^-1 V
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) M[i][j] = Ri[i][0] * V[0][j] + Ri[i][1] * V[1][j] + Ri[i][2] * V[2][j];
-  T A[3][3], B[3][3], D[3][3];
+  U A[3][3], B[3][3], D[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      A[i][j] = T(c[tri(i, j)]);
-      B[i][j] = T(c[tri(i + 3, j)]);
-      D[i][j] = T(c[tri(i + 3, j + 3)]);
+      A[i][j] = U(c[tri(i, j)]);
+      B[i][j] = U(c[tri(i + 3, j)]);
+      D[i][j] = U(c[tri(i + 3, j + 3)]);
     }
-  T G[3][3];  // B R^-1
+  U G[3][3];  // B R^-1
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) G[i][j] = B[i][0] * Ri[0][j] + B[i][1] * Ri[1][j] + B[i][2] * Ri[2][j];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    s[i] = static_cast<float>(T(s[i]) + (A[i][0] * q[0] + A[i][1] * q[1] + A[i][2] * q[2]));
-    s[i + 3] = static_cast<float>(T(s[i + 3]) + (B[i][0] * q[0] + B[i][1] * q[1] + B[i][2] * q[2]));
+    s[i] = static_cast<T>(U(s[i]) + (A[i][0] * q[0] + A[i][1] * q[1] + A[i][2] * q[2]));
+    s[i + 3] = static_cast<T>(U(s[i + 3]) + (B[i][0] * q[0] + B[i][1] * q[1] + B[i][2] * q[2]));
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j <= i; ++j)
-      c[tri(i, j)] = static_cast<float>(A[i][0] * M[0][j] + A[i][1] * M[1][j] + A[i][2] * M[2][j]);
+      c[tri(i, j)] = static_cast<T>(A[i][0] * M[0][j] + A[i][1] * M[1][j] + A[i][2] * M[2][j]);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      c[tri(i + 3, j)] = static_cast<float>(B[i][0] * M[0][j] + B[i][1] * M[1][j] + B[i][2] * M[2][j]);
+      c[tri(i + 3, j)] = static_cast<T>(B[i][0] * M[0][j] + B[i][1] * M[1][j] + B[i][2] * M[2][j]);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j <= i; ++j)
-      c[tri(i + 3, j + 3)] = static_cast<float>(D[i][j] - (G[i][0] * B[j][0] + G[i][1] * B[j][1] + G[i][2] * B[j][2]));
-  chi2_out = static_cast<float>(chi2);
+      c[tri(i + 3, j + 3)] = static_cast<T>(D[i][j] - (G[i][0] * B[j][0] + G[i][1] * B[j][1] + G[i][2] * B[j][2]));
+  chi2_out = static_cast<T>(chi2);
   if (!finite6_21(s, c)) return ST_NONFINITE;
   return 0;
 }
 
-KF_DEV int32_t update(float s[6], float c[21], const float m[3], const float v[6], float& chi2) {
-  return update_t<double>(s, c, m, v, chi2);
+// ---------------------------------------------------------------------------
+// Measurements on a layer, in the frame of the prediction.
+//
+// After the surface-constrained transport the position block A of the
+// predicted covariance has an exact null along the radial unit vector n at the
+// predicted point (the crossing stays on the cylinder).  In the orthonormal
+// frame (n, t, z), t = (-n_y, n_x, 0), the residual covariance R = A + V is
+//     R_loc = V_loc + [[0, 0, 0], [0, A_tt, A_tz], [0, A_tz, A_zz]],
+// which is the textbook R rotated, with A's radial row set to its exact value
+// 0.  Computing it this way keeps the hit's radial variance intact even when
+// the stored A is huge (a vague seed: rounding noise of A along n would swamp
+// V_nn in the global frame).  chi2 and the gain are rotation invariant, so
+// the results equal the global-frame formulas.
+template <typename T>
+struct LocalPred {
+  T nx, ny, tx, ty;  // radial and tangential unit vectors at the prediction
+  T att, atz, azz;   // A in the (t, z) plane
+};
+
+template <typename T>
+KF_DEV LocalPred<T> local_pred(const T s[6], const T c[21]) {
+  LocalPred<T> L;
+  const T ir = rsqrt_t(s[0] * s[0] + s[1] * s[1]);
+  L.nx = s[0] * ir;
+  L.ny = s[1] * ir;
+  L.tx = -L.ny;
+  L.ty = L.nx;
+  L.att = L.tx * L.tx * c[0] + T(2) * L.tx * L.ty * c[1] + L.ty * L.ty * c[2];
+  L.atz = L.tx * c[3] + L.ty * c[4];
+  L.azz = c[5];
+  return L;
+}
+
+// R_loc (packed nn, nt, tt, nz, tz, zz) from the hit covariance v (packed
+// global xx, yx, yy, zx, zy, zz) and the predicted (t, z) block.
+template <typename T>
+KF_DEV void r_local(T nx, T ny, T tx, T ty, T att, T atz, T azz, const float v[6], T r[6]) {
+  const T vxx = T(v[0]), vyx = T(v[1]), vyy = T(v[2]), vzx = T(v[3]), vzy = T(v[4]), vzz = T(v[5]);
+  r[0] = nx * nx * vxx + T(2) * nx * ny * vyx + ny * ny * vyy;
+  r[1] = nx * tx * vxx + (nx * ty + ny * tx) * vyx + ny * ty * vyy;
+  r[2] = tx * tx * vxx + T(2) * tx * ty * vyx + ty * ty * vyy + att;
+  r[3] = nx * vzx + ny * vzy;
+  r[4] = tx * vzx + ty * vzy + atz;
+  r[5] = vzz + azz;
+}
+
+// chi2 of hit (m, v) against a prediction on its layer.
+template <typename T>
+KF_DEV int32_t chi2_on_layer(const T s[6], const LocalPred<T>& L, const float m[3], const float v[6], T& chi2) {
+  T r[6], ri[6];
+  r_local<T>(L.nx, L.ny, L.tx, L.ty, L.att, L.atz, L.azz, v, r);
+  if (!inv3_packed<T>(r, ri)) return ST_NOT_PD;
+  const T dx = T(m[0]) - s[0], dy = T(m[1]) - s[1], dz = T(m[2]) - s[2];
+  const T rn = L.nx * dx + L.ny * dy, rt = L.tx * dx + L.ty * dy;
+  const T q0 = ri[0] * rn + ri[1] * rt + ri[3] * dz;
+  const T q1 = ri[1] * rn + ri[2] * rt + ri[4] * dz;
+  const T q2 = ri[3] * rn + ri[4] * rt + ri[5] * dz;
+  chi2 = rn * q0 + rt * q1 + dz * q2;
+  return 0;
+}
+
+// Kalman update of a prediction on its layer, in the prediction's frame and in
+// precision U.  With U_c = C H^T Q (6x3, Q = [n t z]; its n column is exactly 0):
+//   x'' = x' + U_c R_loc^-1 r_loc,
+//   C''_pos = (A Q) R_loc^-1 V_loc Q^T,  C''_mom,pos = (B Q) R_loc^-1 V_loc Q^T,
+//   C''_mom = D - (B Q) R_loc^-1 (B Q)^T,
+// the stable block forms of C - K H C written in the local frame.
+template <typename T, typename U>
+KF_DEV int32_t update_on_layer(T s[6], T c[21], const float m[3], const float v[6], T& chi2_out) {
+  const U x = U(s[0]), y = U(s[1]);
+  const U ir = U(1) / sqrt(x * x + y * y);
+  const U nx = x * ir, ny = y * ir, tx = -ny, ty = nx;
+  U ut[6], uz[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    ut[i] = U(c[tri(i, 0)]) * tx + U(c[tri(i, 1)]) * ty;
+    uz[i] = U(c[tri(i, 2)]);
+  }
+  const U att = tx * ut[0] + ty * ut[1];
+  const U atz = uz[0] * tx + uz[1] * ty;
+  const U azz = uz[2];
+  U r[6], ri[6];
+  r_local<U>(nx, ny, tx, ty, att, atz, azz, v, r);
+  if (!inv3_packed<U>(r, ri)) return ST_NOT_PD;
+  const U dx = U(m[0]) - x, dy = U(m[1]) - y, dz = U(m[2]) - U(s[2]);
+  const U rl[3] = {nx * dx + ny * dy, tx * dx + ty * dy, dz};
+  const U Ri[3][3] = {{ri[0], ri[1], ri[3]}, {ri[1], ri[2], ri[4]}, {ri[3], ri[4], ri[5]}};
+  U q[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) q[i] = Ri[i][0] * rl[0] + Ri[i][1] * rl[1] + Ri[i][2] * rl[2];
+  const U chi2 = rl[0] * q[0] + rl[1] * q[1] + rl[2] * q[2];
+  // V_loc: R_loc without the A part
+  const U Vl[3][3] = {{r[0], r[1], r[3]}, {r[1], r[2] - att, r[4] - atz}, {r[3], r[4] - atz, r[5] - azz}};
+  // t and z rows of R_loc^-1 V_loc (the n column of U_c is 0)
+  U Ml[2][3];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Ml[a][j] = Ri[a + 1][0] * Vl[0][j] + Ri[a + 1][1] * Vl[1][j] + Ri[a + 1][2] * Vl[2][j];
+  const U Q[3][3] = {{nx, tx, U(0)}, {ny, ty, U(0)}, {U(0), U(0), U(1)}};  // columns n, t, z
+  U P[6][3];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P[i][k] = ut[i] * Ml[0][k] + uz[i] * Ml[1][k];
+  U dn[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) dn[i] = ut[i] * q[1] + uz[i] * q[2];
+  U Dn[6];
+  {
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        const U gi1 = ut[3 + i] * Ri[1][1] + uz[3 + i] * Ri[2][1];
+        const U gi2 = ut[3 + i] * Ri[1][2] + uz[3 + i] * Ri[2][2];
+        Dn[k++] = U(c[tri(3 + i, 3 + j)]) - (gi1 * ut[3 + j] + gi2 * uz[3 + j]);
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) s[i] = static_cast<T>(U(s[i]) + dn[i]);
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 3 && j <= i; ++j)
+      c[tri(i, j)] = static_cast<T>(P[i][0] * Q[j][0] + P[i][1] * Q[j][1] + P[i][2] * Q[j][2]);
+  {
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) c[tri(3 + i, 3 + j)] = static_cast<T>(Dn[k++]);
+  }
+  chi2_out = static_cast<T>(chi2);
+  if (!finite6_21(s, c)) return ST_NONFINITE;
+  return 0;
 }
 
 }  // namespace kfd

@@ -14,21 +14,24 @@ namespace {
 
 thread_local std::string g_last_error = "no error";
 
-// Coalesced SoA loads/stores of one track's state and packed covariance.
+// Coalesced SoA loads/stores of one track's state and packed covariance
+// (float32 in HBM, T in registers).
+template <typename T>
 __device__ __forceinline__ void load_track(const float* __restrict__ st, const float* __restrict__ cv, int64_t ld,
-                                           int64_t i, float s[6], float c[21]) {
+                                           int64_t i, T s[6], T c[21]) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) s[k] = __builtin_nontemporal_load(st + k * ld + i);
+  for (int k = 0; k < 6; ++k) s[k] = T(__builtin_nontemporal_load(st + k * ld + i));
 #pragma unroll
-  for (int k = 0; k < 21; ++k) c[k] = __builtin_nontemporal_load(cv + k * ld + i);
+  for (int k = 0; k < 21; ++k) c[k] = T(__builtin_nontemporal_load(cv + k * ld + i));
 }
 
+template <typename T>
 __device__ __forceinline__ void store_track(float* __restrict__ st, float* __restrict__ cv, int64_t ld, int64_t i,
-                                            const float s[6], const float c[21]) {
+                                            const T s[6], const T c[21]) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(s[k], st + k * ld + i);
+  for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(static_cast<float>(s[k]), st + k * ld + i);
 #pragma unroll
-  for (int k = 0; k < 21; ++k) __builtin_nontemporal_store(c[k], cv + k * ld + i);
+  for (int k = 0; k < 21; ++k) __builtin_nontemporal_store(static_cast<float>(c[k]), cv + k * ld + i);
 }
 
 __global__ void __launch_bounds__(256) propagate_kernel(int64_t n, int64_t ld, float* state, float* cov,
@@ -40,7 +43,7 @@ __global__ void __launch_bounds__(256) propagate_kernel(int64_t n, int64_t ld, f
   if (i >= n) return;
   float s[6], c[21];
   load_track(state, cov, ld, i, s, c);
-  const float a = -static_cast<float>(charge[i]) * kCLight * g.bz;
+  const float a = static_cast<float>(-static_cast<double>(charge[i]) * kCLight * g.bz);
   int32_t st = 0;
   if (material_layer >= 0) {
     if (!finite6_21(s, c))
@@ -70,12 +73,14 @@ __global__ void __launch_bounds__(256) update_kernel(int64_t n, int64_t ld, floa
   int32_t st;
   if (!finite6_21(s, c)) {
     st = ST_NONFINITE;
-  } else if (chi2_only) {
-    float ri[6], r[3];
-    st = chi2_of(s, c, m, v, ri, r, c2);
   } else {
-    st = update(s, c, m, v, c2);
-    if (!st) store_track(state, cov, ld, i, s, c);
+    float s2[6], cc[21];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s2[k] = s[k];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) cc[k] = c[k];
+    st = update_global<float, double>(s2, cc, m, v, c2);
+    if (!st && !chi2_only) store_track(state, cov, ld, i, s2, cc);
   }
   chi2[i] = st ? 0.f : c2;
   status[i] = st;
@@ -85,29 +90,33 @@ __global__ void __launch_bounds__(256) update_kernel(int64_t n, int64_t ld, floa
 // q/pT, cot(theta), z/z_half, sin(phi_dir - phi_pos), r_from/100, r_to/100,
 // log sigma_rphi, log sigma_z of the predicted position; targets are the
 // tangential and z offsets of the track's own hit from the prediction.
-__device__ __forceinline__ void emit_residual(float* __restrict__ out, int64_t ldr, int64_t row, const float s[6],
-                                              const float c[21], float q, float r_from, float r_to, float zh,
+template <typename T>
+__device__ __forceinline__ void emit_residual(float* __restrict__ out, int64_t ldr, int64_t row, const T s[6],
+                                              const T c[21], float q, float r_from, float r_to, float zh,
                                               const float m[3]) {
-  const float ipt = __frsqrt_rn(s[3] * s[3] + s[4] * s[4]);
-  const float ir = __frsqrt_rn(s[0] * s[0] + s[1] * s[1]);
-  const float tx = -s[1] * ir, ty = s[0] * ir;  // tangential unit vector
-  const float ctt = tx * tx * c[0] + 2.f * tx * ty * c[1] + ty * ty * c[2];
+  const float x = float(s[0]), y = float(s[1]), z = float(s[2]), px = float(s[3]), py = float(s[4]),
+              pz = float(s[5]);
+  const float ipt = __frsqrt_rn(px * px + py * py);
+  const float ir = __frsqrt_rn(x * x + y * y);
+  const float tx = -y * ir, ty = x * ir;  // tangential unit vector
+  const float ctt = tx * tx * float(c[0]) + 2.f * tx * ty * float(c[1]) + ty * ty * float(c[2]);
   const float f[KF_RES_FEATURES + 2] = {
       q * ipt,
-      s[5] * ipt,
-      s[2] / zh,
-      (s[0] * s[4] - s[1] * s[3]) * ipt * ir,
+      pz * ipt,
+      z / zh,
+      (x * py - y * px) * ipt * ir,
       r_from * 0.01f,
       r_to * 0.01f,
       0.5f * logf(fmaxf(ctt, 1e-30f)),
-      0.5f * logf(fmaxf(c[5], 1e-30f)),
-      tx * (m[0] - s[0]) + ty * (m[1] - s[1]),
-      m[2] - s[2],
+      0.5f * logf(fmaxf(float(c[5]), 1e-30f)),
+      tx * (m[0] - x) + ty * (m[1] - y),
+      m[2] - z,
   };
 #pragma unroll
   for (int k = 0; k < KF_RES_FEATURES + 2; ++k) out[k * ldr + row] = f[k];
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const float* state_in,
                                                   const float* cov_in, const int8_t* __restrict__ charge,
                                                   const int32_t* __restrict__ hit_idx, int64_t ld_idx,
@@ -119,14 +128,14 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int L = g.n_layers;
-  float s[6], c[21];
+  T s[6], c[21];
   load_track(state_in, cov_in, ld, i, s, c);
   const float qf = static_cast<float>(charge[i]);
-  const float a = -qf * kCLight * g.bz;
+  const T a = T(-static_cast<double>(charge[i]) * kCLight * g.bz);
   int last = -1;
   for (int l = 0; l < L; ++l)
     if (hit_idx[l * ld_idx + i] >= 0) last = l;
-  float chi2 = 0.f;
+  T chi2 = T(0);
   int32_t nh = 0, st = 0;
   if (res) {
     for (int l = 1; l < L; ++l)
@@ -135,22 +144,23 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
   }
   float r_from = 0.f;
   for (int l = 0; l <= last; ++l) {
-    float s2[6], c2[21];
+    T s2[6], c2[21];
 #pragma unroll
     for (int k = 0; k < 6; ++k) s2[k] = s[k];
 #pragma unroll
     for (int k = 0; k < 21; ++k) c2[k] = c[k];
-    st = propagate(s2, c2, a, g.r[l], 0.f);
+    st = propagate(s2, c2, a, T(g.r[l]), T(0));
     if (st) break;
     const int32_t h = hit_idx[l * ld_idx + i];
     if (h >= 0) {
-      float m[3], v[6], dc2;
+      float m[3], v[6];
+      T dc2;
 #pragma unroll
       for (int k = 0; k < 3; ++k) m[k] = hit_pos[k * ldh + h];
 #pragma unroll
       for (int k = 0; k < 6; ++k) v[k] = hit_cov[k * ldh + h];
       if (res && l >= 1) emit_residual(res, ldr, i * (L - 1) + (l - 1), s2, c2, qf, r_from, g.r[l], g.z_half[l], m);
-      st = update(s2, c2, m, v, dc2);
+      st = update_on_layer<T, double>(s2, c2, m, v, dc2);
       if (st) break;
       chi2 += dc2;
       nh += 1;
@@ -161,7 +171,7 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
     for (int k = 0; k < 21; ++k) c[k] = c2[k];
     r_from = g.r[l];
     if (l < last) {
-      st = material(s2, c2, g.x_over_x0[l], g.eloss_per_x0, g.mass);
+      st = material(s2, c2, T(g.x_over_x0[l]), T(g.eloss_per_x0), T(g.mass));
       if (st) break;
 #pragma unroll
       for (int k = 0; k < 6; ++k) s[k] = s2[k];
@@ -170,7 +180,7 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
     }
   }
   store_track(state_out, cov_out, ld, i, s, c);
-  chi2_out[i] = chi2;
+  chi2_out[i] = static_cast<float>(chi2);
   nhits_out[i] = nh;
   status_out[i] = st;
 }
@@ -285,7 +295,7 @@ int32_t kf_fit(kf_ctx* ctx, const kf_fit_args* a) {
   const int L = ctx->geom.n_layers;
   if (a->n < 0 || a->ld < a->n || a->ld_idx < a->n || a->ldh < 0)
     return set_error(KF_ERR_INVALID_ARG, "bad sizes");
-  if (a->flags & ~KF_FIT_EMIT_RESIDUALS) return set_error(KF_ERR_INVALID_ARG, "unknown flags %u", a->flags);
+  if (a->flags & ~(KF_FIT_EMIT_RESIDUALS | KF_FIT_FP64)) return set_error(KF_ERR_INVALID_ARG, "unknown flags %u", a->flags);
   const bool emit = (a->flags & KF_FIT_EMIT_RESIDUALS) != 0;
   if (emit && (!a->residual_out || L < 2 || a->ld_res < a->n * (L - 1)))
     return set_error(KF_ERR_INVALID_ARG, "residual_out missing or ld_res < n * (n_layers - 1)");
@@ -293,7 +303,8 @@ int32_t kf_fit(kf_ctx* ctx, const kf_fit_args* a) {
   if (!a->state_in || !a->cov_in || !a->charge || !a->hit_idx || !a->state_out || !a->cov_out || !a->chi2_out ||
       !a->nhits_out || !a->status_out)
     return set_error(KF_ERR_INVALID_ARG, "null array");
-  fit_kernel<<<kfh::grid_for(a->n, 256), 256, 0, kfh::stream_of(a->stream)>>>(
+  auto kern = (a->flags & KF_FIT_FP64) ? fit_kernel<double> : fit_kernel<float>;
+  kern<<<kfh::grid_for(a->n, 256), 256, 0, kfh::stream_of(a->stream)>>>(
       a->n, a->ld, a->state_in, a->cov_in, a->charge, a->hit_idx, a->ld_idx, a->hit_pos, a->hit_cov, a->ldh,
       a->state_out, a->cov_out, a->chi2_out, a->nhits_out, a->status_out, ctx->dgeom,
       emit ? a->residual_out : nullptr, a->ld_res);

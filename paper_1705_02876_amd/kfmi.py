@@ -21,6 +21,7 @@ KF_OK = 0
 ST_NO_CROSSING, ST_OUT_OF_Z, ST_NONFINITE, ST_NOT_PD, ST_STOPPED = 1, 2, 4, 8, 16
 UPDATE_CHI2_ONLY = 1
 FIT_EMIT_RESIDUALS = 1
+FIT_FP64 = 2
 RES_FEATURES = 8
 
 
@@ -191,7 +192,7 @@ class Context:
                               _ptr(chi2), _ptr(status), UPDATE_CHI2_ONLY if chi2_only else 0, _stream(stream)))
 
     def kf_fit(self, state_in, cov_in, charge, hit_idx, hit_pos, hit_cov, state_out, cov_out, chi2_out, nhits_out,
-               status_out, residual_out=None, n=None, stream=None):
+               status_out, residual_out=None, n=None, stream=None, fp64=False):
         import torch
         for t, dt, nm in ((state_in, torch.float32, "state_in"), (cov_in, torch.float32, "cov_in"),
                           (charge, torch.int8, "charge"), (hit_idx, torch.int32, "hit_idx"),
@@ -208,8 +209,9 @@ class Context:
         a.hit_pos, a.hit_cov, a.ldh = _ptr(hit_pos), _ptr(hit_cov), hit_pos.shape[1]
         a.state_out, a.cov_out, a.chi2_out = _ptr(state_out), _ptr(cov_out), _ptr(chi2_out)
         a.nhits_out, a.status_out = _ptr(nhits_out), _ptr(status_out)
+        a.flags = FIT_FP64 if fp64 else 0
         if residual_out is not None:
-            a.flags = FIT_EMIT_RESIDUALS
+            a.flags |= FIT_EMIT_RESIDUALS
             a.residual_out = _ptr(residual_out)
             a.ld_res = residual_out.shape[1]
         a.stream = _stream(stream)

@@ -6,6 +6,7 @@ import ctypes as C
 BINNED_FLOATS = 12
 BUILD_TILED, BUILD_PERSISTENT = 0, 1
 WINDOW_PLAIN, WINDOW_LEARNED = 0, 1
+PREC_F32, PREC_F64 = 0, 1
 
 
 class kf_bin_args(C.Structure):
@@ -21,7 +22,7 @@ class kf_build_cfg(C.Structure):
     _fields_ = [
         ("max_cands", C.c_int32), ("chi2_cut", C.c_float), ("n_phi", C.c_int32), ("n_eta", C.c_int32),
         ("window_margin", C.c_float), ("mode", C.c_int32), ("window_mode", C.c_int32),
-        ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
+        ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("precision", C.c_int32),
     ]
 
 
@@ -97,9 +98,9 @@ def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16,
 
 
 def make_cfg(max_cands=6, chi2_cut=30.0, n_phi=64, n_eta=16, window_margin=0.01, mode=BUILD_TILED,
-             window_mode=WINDOW_PLAIN, waves_per_block=0, blocks_per_cu=0):
+             window_mode=WINDOW_PLAIN, waves_per_block=0, blocks_per_cu=0, precision=PREC_F64):
     return kf_build_cfg(max_cands, chi2_cut, n_phi, n_eta, window_margin, mode, window_mode, waves_per_block,
-                        blocks_per_cu)
+                        blocks_per_cu, precision)
 
 
 def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=None, counters=None, workspace=None,

@@ -11,9 +11,9 @@ simulated track, a simplified detector of equally spaced fixed-length
 concentric cylinders, and in-house simulation with Gaussian smearing of the
 hit positions.  Nothing here runs the Kalman filter: the truth trajectory is
 stepped with the exact circle/circle intersection of the track's transverse
-circle with each layer, and seeds are the helix through the vertex fitted to
-three hits, with a covariance from finite-difference error propagation of the
-hit errors.
+circle with each layer.  Seed covariances come from the helix through the
+vertex fitted to the first three hits (finite-difference error propagation of
+the hit errors), seed means are drawn around the truth at the third hit.
 
 All arithmetic is float64; callers cast to float32 for the GPU and pass the
 float32-rounded values back to the oracle so both sides see identical inputs.
@@ -492,6 +492,42 @@ def seeds_from_hits(hits3, det: Detector, ms_layers=2):
     return st, C, q
 
 
+SEED_MAX_REL_MOMENTUM_SIGMA = 0.15
+
+
+def truth_seeds(rng, sim, det: Detector, draw=True):
+    """Seeds at the third hit: covariance from the three-hit fit (seeds_from_hits) with the
+    momentum block's eigenvalues capped at (0.15 p)^2, mean = truth at the third layer plus a
+    draw from that covariance, charge = truth.
+
+    Realistic seeding is outside the method (the paper reports none); a Gaussian in
+    Cartesian momentum cannot describe a curvature that is consistent with zero, so the
+    three-hit estimate alone gives meaningless priors for stiff tracks.
+    """
+    h3 = sim["hit_pos"][0:3]
+    _, C, _ = seeds_from_hits(h3, det)
+    truth = np.concatenate([sim["true_pos"][2], sim["true_mom"][2]], axis=1)
+    p = np.linalg.norm(truth[:, 3:], axis=1)
+    w, V = np.linalg.eigh(C[:, 3:, 3:])
+    cap = (SEED_MAX_REL_MOMENTUM_SIGMA * p) ** 2
+    wc = np.minimum(w, cap[:, None])
+    scale = np.sqrt(np.where(w > 0, wc / np.where(w > 0, w, 1.0), 1.0))  # shrink factor per eigen-direction
+    # C' = S C S^T with S = I on positions and V diag(scale) V^T on momenta keeps the
+    # cross-correlations consistent with the shrunk momentum block
+    Sm = np.einsum("nij,nj,nkj->nik", V, scale, V)
+    Sfull = np.zeros_like(C)
+    Sfull[:, :3, :3] = np.eye(3)
+    Sfull[:, 3:, 3:] = Sm
+    Cc = Sfull @ C @ np.transpose(Sfull, (0, 2, 1))
+    Cc = 0.5 * (Cc + np.transpose(Cc, (0, 2, 1)))
+    if not draw:
+        return truth.copy(), Cc, sim["q"].copy()
+    w2, V2 = np.linalg.eigh(Cc)
+    g = rng.standard_normal((truth.shape[0], 6)) * np.sqrt(np.maximum(w2, 0.0))
+    st = truth + np.einsum("nij,nj->ni", V2, g)
+    return st, Cc, sim["q"].copy()
+
+
 # ----------------------------------------------------------------------------
 # build workloads (events with noise hits, seeds)
 # ----------------------------------------------------------------------------
@@ -515,7 +551,7 @@ class BuildProblem:
 
 
 def make_build_problem(track_counts, det: Detector, seed, p_miss=0.05, noise_frac=0.2, smear=True,
-                       pt_range=(0.5, 10.0), eta_range=(-1.0, 1.0)):
+                       pt_range=(0.5, 10.0), eta_range=(-1.0, 1.0), seed_draw=True):
     """Events of sim tracks plus `noise_frac * n_tracks` uniform noise hits per layer.
 
     The first three layers always carry the track's hit; one seed per track.
@@ -557,9 +593,8 @@ def make_build_problem(track_counts, det: Detector, seed, p_miss=0.05, noise_fra
             pos_chunks.append(allpos)
             trk_chunks.append(alltrk)
             offs.append(base + allpos.shape[0])
-        # seeds: one per track from its layer 0..2 hits
-        h3 = sim["hit_pos"][0:3]
-        st, C, q = seeds_from_hits(h3, det)
+        # seeds: one per track, covariance from its layer 0..2 hits, mean drawn around the truth
+        st, C, q = truth_seeds(rng, sim, det, draw=seed_draw)
         seed_state.append(st)
         seed_cov.append(C)
         seed_q.append(q)

@@ -3,8 +3,9 @@ oracle calls on the same float32-rounded values, and the tolerance checks.
 
 Tolerances: track parameters 1e-4 relative (positions relative to the layer
 radius, momentum components relative to |p|), chi2 |d| <= 1e-3 max(chi2, 1),
-covariance |dC_ij| <= 1e-3 sqrt(C_ii C_jj) (plus 1e-9 absolute for the radial
-null direction of positions on a cylinder).
+covariance |dC_ij| <= 1e-3 sqrt(D_i D_j), D = diag(C) with the transverse variance
+C_xx + C_yy used for both x and y (positions on a cylinder have a null radial
+direction).
 """
 from __future__ import annotations
 
@@ -65,13 +66,39 @@ def check_params(gs, os_, name="state", rel=REL_PARAM):
     return worst
 
 
+def cov_scale(oc):
+    """sqrt(D_i D_j) with D = diag(C), except that x and y both use the transverse
+    variance C_xx + C_yy: a position on a cylinder has no radial variance, so one
+    of C_xx, C_yy vanishes where the radial direction is along an axis."""
+    d = np.maximum(np.diagonal(oc, axis1=1, axis2=2), 0.0).copy()
+    t = d[:, 0] + d[:, 1]
+    d[:, 0] = t
+    d[:, 1] = t
+    d = np.sqrt(d)
+    return d[:, :, None] * d[:, None, :] + 1e-30
+
+
 def check_cov(gc, oc, name="cov", rel=REL_COV):
-    d = np.sqrt(np.maximum(np.diagonal(oc, axis1=1, axis2=2), 0.0))
-    scale = d[:, :, None] * d[:, None, :] + 1e-9
+    scale = cov_scale(oc)
     err = np.abs(gc - oc) / scale
     worst = err.max(initial=0)
     assert worst <= rel, f"{name}: worst relative covariance error {worst:.3g}"
     return worst
+
+
+GRAZING_COS = 0.2
+
+
+def min_cos_psi(fp):
+    """Smallest |cos| of the angle between the truth momentum and the layer normal over
+    the crossings up to each track's last hit (a conditioning measure: the transported
+    covariance grows like 1/cos^2 at grazing crossings)."""
+    tp, tm = fp.extra["true_pos"], fp.extra["true_mom"]
+    c = np.abs((tp[..., 0] * tm[..., 0] + tp[..., 1] * tm[..., 1]) /
+               (np.hypot(tp[..., 0], tp[..., 1]) * np.linalg.norm(tm, axis=2)))
+    L = c.shape[0]
+    mask = np.arange(L)[:, None] <= fp.last_layer[None, :]
+    return np.where(mask & np.isfinite(c), c, np.inf).min(axis=0)
 
 
 def check_chi2(gc, oc, name="chi2", rel=REL_CHI2):

@@ -30,13 +30,13 @@ def ctx():
     c.close()
 
 
-def _gpu_build(ctx, prob, N=6, mode=0, det32=None, counters=False):
+def _gpu_build(ctx, prob, N=6, mode=0, det32=None, counters=False, precision=1):
     import torch
     from paper_1705_02876_amd import kfmi_build as KB
     ctx.kf_set_geometry(det32)
     seeds, hits = KB.upload_problem(prob)
     bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events)
-    cfg = KB.make_cfg(max_cands=N, mode=mode)
+    cfg = KB.make_cfg(max_cands=N, mode=mode, precision=precision)
     cnt = torch.zeros(5, dtype=torch.int64, device="cuda") if counters else None
     out = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, counters=cnt)
     torch.cuda.synchronize()
@@ -104,26 +104,28 @@ def test_bin_hits_bit_exact(ctx, orc):
     assert np.allclose(vm[nonempty, 1], det.sigma_z ** 2, rtol=1e-5)
 
 
-@pytest.mark.parametrize("N,mode", [(6, 0), (6, 1), (1, 0), (3, 0), (8, 1)])
-def test_build_parity(ctx, orc, N, mode):
+@pytest.mark.parametrize("N,mode,precision", [(6, 0, 1), (6, 1, 1), (1, 0, 1), (3, 0, 1), (8, 1, 1), (6, 0, 0),
+                                              (1, 1, 0)])
+def test_build_parity(ctx, orc, N, mode, precision):
     det = S.detector_full()
     det32 = det.as_float32()
     prob = S.make_build_problem([800, 1500, 3, 0, 1200], det, 62)
-    gpu, _ = _gpu_build(ctx, prob, N=N, mode=mode, det32=det32)
+    gpu, _ = _gpu_build(ctx, prob, N=N, mode=mode, det32=det32, precision=precision)
     ora = _oracle_build(orc, prob, det32, N=N)
-    _compare(gpu, ora, label=f"N={N} mode={mode}")
+    _compare(gpu, ora, label=f"N={N} mode={mode} precision={'f64' if precision else 'f32'}")
 
 
 def test_build_deterministic_and_modes_agree(ctx):
     det = S.detector_full()
     det32 = det.as_float32()
     prob = S.make_build_problem([2500, 700], det, 63)
-    a, _ = _gpu_build(ctx, prob, N=6, mode=0, det32=det32)
-    b, _ = _gpu_build(ctx, prob, N=6, mode=0, det32=det32)
-    c, _ = _gpu_build(ctx, prob, N=6, mode=1, det32=det32)
-    for k in a:
-        assert np.array_equal(a[k], b[k], equal_nan=True), k
-        assert np.array_equal(a[k], c[k], equal_nan=True), k
+    for precision in (0, 1):
+        a, _ = _gpu_build(ctx, prob, N=6, mode=0, det32=det32, precision=precision)
+        b, _ = _gpu_build(ctx, prob, N=6, mode=0, det32=det32, precision=precision)
+        c, _ = _gpu_build(ctx, prob, N=6, mode=1, det32=det32, precision=precision)
+        for k in a:
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
+            assert np.array_equal(a[k], c[k], equal_nan=True), k
 
 
 def test_build_edge_cases(ctx, orc):
@@ -163,13 +165,15 @@ def test_build_rejects_bad_config(ctx):
         KB.build(ctx, KB.make_cfg(), seeds, bins, hits["layer_offsets"], prob.n_events, first_layer=2)
 
 
-def test_build_full_size_sampled(ctx, orc):
-    """16 events of U{5k..20k} tracks (the build workload, its launch); 600 sampled seeds against the oracle."""
+@pytest.mark.parametrize("precision", [0, 1])
+def test_build_full_size_sampled(ctx, orc, precision):
+    """16 events of U{5k..20k} tracks (the build workload) in the persistent launch the bench times;
+    600 sampled seeds against the oracle."""
     from paper_1705_02876_amd import workloads as W
     det = S.detector_full()
     det32 = det.as_float32()
     prob = W.build_workload(16, det)
-    gpu, _ = _gpu_build(ctx, prob, N=6, mode=0, det32=det32, counters=True)
+    gpu, _ = _gpu_build(ctx, prob, N=6, mode=1, det32=det32, counters=True, precision=precision)
     rng = np.random.Generator(np.random.PCG64(3))
     sel = np.sort(rng.choice(prob.seed_state.shape[0], 600, replace=False))
     ora = _oracle_build(orc, prob, det32, N=6, seeds=sel)

@@ -184,7 +184,7 @@ def test_n1_is_greedy_best_hit(orc):
 def test_noiseless_events_fully_found(orc):
     det = S.Detector(radii=S.detector_full().radii, x_over_x0=0.0)
     g = orc.geometry(det)
-    prob = S.make_build_problem([300], det, 37, p_miss=0.0, noise_frac=0.0, smear=False)
+    prob = S.make_build_problem([300], det, 37, p_miss=0.0, noise_frac=0.0, smear=False, seed_draw=False)
     out = orc.build(g, prob, max_cands=6, mode=1)
     r = judge.judge_problem(prob, out["cand_hits"][:, 0, :])
     assert r["eff"] == 1.0 and r["n_fake"] == 0
