@@ -277,6 +277,40 @@ typedef struct {
 size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_seeds);
 int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* args);
 
+
+/* ------------------------------------------------------------------------
+ * Learned search window (project addition beyond the paper): a network
+ * 8 -> 64 -> 64 -> 2 with ReLU hidden layers maps the features of a
+ * prediction (see KF_FIT_EMIT_RESIDUALS) to o = (log s_t, log s_z), the
+ * scales of the tangential and z offsets of the track's own hit.  Training
+ * minimises the mean Gaussian negative log-likelihood
+ *     l = sum_k [ r_k^2 exp(-2 o_k) / 2 + o_k ]
+ * over records; the optimiser is Adam.  Matrix products run on the bf16
+ * matrix cores with float32 accumulation.
+ * Parameters (device, float32): KF_MLP_PARAMS values in the order W1 [64][8],
+ * b1 [64], W2 [64][64], b2 [64], W3 [2][64], b3 [2] (row-major).
+ * kf_mlp_pack converts them to the kernels' layout, a device buffer of
+ * KF_MLP_PACKED_BYTES bytes (bf16 matrix-core operand tiles + float32 biases).
+ * Records: x [KF_RES_FEATURES][ldx], targets t [2][ldt], outputs y [2][ldy]
+ * (float32 device arrays; rows with any non-finite entry are skipped by
+ * kf_mlp_grad and give NaN in kf_mlp_forward). */
+#define KF_MLP_PARAMS 4866
+#define KF_MLP_PACKED_BYTES 23048
+int32_t kf_mlp_pack(kf_ctx* ctx, const float* params, void* packed, void* stream);
+int32_t kf_mlp_forward(kf_ctx* ctx, int64_t n, const float* x, int64_t ldx, const void* packed, float* y, int64_t ldy,
+                       void* stream);
+/* Mean loss and its gradient over the n records: grad [KF_MLP_PARAMS]
+ * (same order as the parameters), loss [1], count [1] (records used, as a
+ * float).  Workspace: kf_mlp_grad_workspace_size() bytes.  Deterministic. */
+size_t kf_mlp_grad_workspace_size(void);
+int32_t kf_mlp_grad(kf_ctx* ctx, int64_t n, const float* x, int64_t ldx, const float* t, int64_t ldt,
+                    const void* packed, float* grad, float* loss, float* count, void* workspace,
+                    size_t workspace_bytes, void* stream);
+/* One Adam step (bias-corrected, step >= 1) on params from grad, with first
+ * and second moments m, v [KF_MLP_PARAMS]; then repacks into packed. */
+int32_t kf_mlp_adam(kf_ctx* ctx, float* params, const float* grad, float* m, float* v, int32_t step, float lr,
+                    float beta1, float beta2, float eps, void* packed, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,10 @@ minimises the Gaussian negative log-likelihood per record
     l = sum_k [ r_k^2 exp(-2 o_k) / 2 + o_k ],
 averaged over the batch; the optimiser is Adam (Kingma & Ba, 2015) with
 bias-corrected moments.  Parameters are kept in a dict of float64 arrays.
+
+round_bf16 is the bfloat16 format's definition (8 significant bits, round to
+nearest, ties to even), used to state the network as a device holds it: its
+weights in bfloat16.
 """
 from __future__ import annotations
 
@@ -48,6 +52,22 @@ def unflatten(v):
         p[f"b{i + 1}"] = v[off:off + fo].copy()
         off += fo
     return p
+
+
+def round_bf16(a):
+    """Nearest bfloat16 value of each element (ties to even), returned as float64."""
+    a = np.asarray(a, dtype=np.float64)
+    _, e = np.frexp(a)  # |a| = m 2^e with 0.5 <= m < 1
+    # spacing of bfloat16 values around a: 2^(e-8), and 2^-133 in the subnormal range
+    quantum = np.ldexp(1.0, np.maximum(e, -125) - 8)
+    with np.errstate(invalid="ignore"):
+        out = np.round(a / quantum) * quantum  # numpy rounds halves to even
+    return np.where(np.isfinite(a), out, a)
+
+
+def bf16_params(p):
+    """The parameters as the device network holds them: weights in bfloat16, biases in float32."""
+    return {k: (round_bf16(v) if k.startswith("W") else v.astype(np.float32).astype(np.float64)) for k, v in p.items()}
 
 
 def forward(p, X):

@@ -89,8 +89,9 @@ def load_library(path=LIB_PATH):
 
 def _declare_more(lib):
     """Declarations of the building / batching / learned-window calls (see kfmi.h)."""
-    from . import kfmi_build
+    from . import kfmi_build, kfmi_mlp
     kfmi_build.declare(lib)
+    kfmi_mlp.declare(lib)
 
 
 def header_symbols(path=HEADER):

@@ -624,3 +624,25 @@ def loguniform_event_sizes(seed, n_events, lo=1000, hi=50000):
 def round_f32(x):
     """Round a float64 array to float32 and back (the values both sides see)."""
     return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def window_records(seed, n):
+    """Synthetic training records for the search-window network: 8 features in the
+    ranges a fit prediction produces (q/pT, cot theta, z/z_half, sin of the crossing
+    angle, r_from/100, r_to/100, log sigma_t, log sigma_z of the prediction) and two
+    Gaussian offsets whose widths grow with the prediction's sigmas and with
+    |q/pT| (multiple scattering).  Returns x (n, 8), t (n, 2) float64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    qpt = rng.choice([-1.0, 1.0], n) / rng.uniform(0.5, 10.0, n)
+    cot = np.sinh(rng.uniform(-1.0, 1.0, n))
+    r_from = rng.integers(0, 16, n) * 0.06 + 0.04
+    r_to = r_from + 0.06
+    z = np.clip(cot * r_to * 100.0 / 50.0, -1.0, 1.0)
+    sin_cross = np.clip(0.5 * 0.0114 * r_to * 100.0 * qpt, -1.0, 1.0)
+    lst = rng.uniform(-5.5, -2.0, n)
+    lsz = rng.uniform(-4.0, -1.5, n)
+    x = np.stack([qpt, cot, z, sin_cross, r_from, r_to, lst, lsz], axis=1)
+    st = np.sqrt(np.exp(2 * lst) + 0.01 ** 2 + (0.004 * np.abs(qpt)) ** 2)
+    sz = np.sqrt(np.exp(2 * lsz) + 0.1 ** 2 / 12 + (0.004 * np.abs(qpt) * np.sqrt(1 + cot ** 2)) ** 2)
+    t = np.stack([st * rng.standard_normal(n), sz * rng.standard_normal(n)], axis=1)
+    return x, t
