@@ -89,7 +89,7 @@ BUILD_FLOP_UPDATE = FLOP_PER_HIT
 
 
 def build_flops(cnt):
-    box, chi2, comp, steps, upd = [int(x) for x in cnt]
+    box, chi2, comp, steps, upd = [int(x) for x in cnt[:5]]
     return BUILD_FLOP_STEP * steps + BUILD_FLOP_BOX * box + BUILD_FLOP_CHI2 * chi2 + BUILD_FLOP_UPDATE * upd
 
 
@@ -193,7 +193,7 @@ def main():
     bws_bytes = kfmi.load_library().kf_bin_hits_workspace_size(hits["pos"].shape[1])
     bws = torch.empty(max(bws_bytes, 4), dtype=torch.uint8, device=dev)
     bout = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events)
-    cnt = torch.zeros(5, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(KB.BUILD_COUNTERS, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
 
     def fit_step():

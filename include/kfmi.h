@@ -225,14 +225,20 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* args);
  *   and best_cov [21][ld_seed] of the rank-0 candidate (nullable);
  *   counters [KF_BUILD_COUNTERS] uint64 (nullable, accumulated): hits
  *   box-tested, chi2 evaluations, compatible hits, candidate-layer steps,
- *   survivor updates with a hit.
+ *   survivor updates with a hit, learned-window fallbacks to the plain window.
  * Modes: KF_BUILD_TILED (default) runs every layer of a tile of seeds inside
  * one launch; KF_BUILD_PERSISTENT launches one grid sized to the device
  * whose waves pull tiles from a device work queue (needs workspace).
- * window_mode KF_WINDOW_LEARNED uses the network given by kf_build_set_mlp
- * (see below) and falls back to the plain window for a candidate when no hit
- * passes in the learned one. */
-#define KF_BUILD_COUNTERS 5
+ * Windows: a candidate's compatible hits are those with chi2 < chi2_cut.  The
+ * plain window (KF_WINDOW_PLAIN) only limits the bins scanned: it bounds the
+ * chi2 < chi2_cut region, so it changes no result.  KF_WINDOW_LEARNED (a
+ * project addition) evaluates the search-window network (see below, weights in
+ * args->mlp_packed) on the candidate's prediction, giving scales (s_t, s_z);
+ * compatible hits must then also lie within learned_nsigma * s_t along the
+ * layer's tangential direction and learned_nsigma * s_z in z of the predicted
+ * position; if no hit of the layer passes both, the candidate falls back to
+ * the plain definition for that layer (counted). */
+#define KF_BUILD_COUNTERS 6
 #define KF_BUILD_TILED 0
 #define KF_BUILD_PERSISTENT 1
 #define KF_WINDOW_PLAIN 0
@@ -249,6 +255,7 @@ typedef struct {
   int32_t waves_per_block; /* 0 = library choice */
   int32_t blocks_per_cu;   /* persistent mode occupancy, 0 = library choice */
   int32_t precision;       /* KF_PREC_F32 or KF_PREC_F64: candidate registers (HBM is float32 either way) */
+  float learned_nsigma;    /* KF_WINDOW_LEARNED: half widths in units of the network's scales, > 0 */
 } kf_build_cfg;
 typedef struct {
   int64_t n_events, n_seeds, ld_seed;
@@ -273,6 +280,7 @@ typedef struct {
   void* workspace;
   size_t workspace_bytes;
   void* stream;
+  const void* mlp_packed; /* KF_WINDOW_LEARNED: KF_MLP_PACKED_BYTES from kf_mlp_pack, else ignored */
 } kf_build_args;
 size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_seeds);
 int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* args);

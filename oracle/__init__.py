@@ -40,6 +40,8 @@ class BuildCfg(C.Structure):
         ("n_phi", C.c_int32),
         ("n_eta", C.c_int32),
         ("window_margin", C.c_double),
+        ("mlp_params", C.c_void_p),
+        ("learned_nsigma", C.c_double),
     ]
 
 
@@ -74,7 +76,13 @@ def _declare(L):
     L.or_bin_hits.restype = C.c_int32
     L.or_bin_hits.argtypes = [P, C.c_int64, P, P, C.c_int32, C.c_int32, P, P, P]
     L.or_build.restype = C.c_int32
-    L.or_build.argtypes = [P, P, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, C.c_int32] + [P] * 10
+    L.or_build.argtypes = [P, P, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, C.c_int32] + [P] * 12
+    L.or_bf16.restype = C.c_double
+    L.or_bf16.argtypes = [C.c_double]
+    L.or_mlp_forward.restype = None
+    L.or_mlp_forward.argtypes = [P, P, P]
+    L.or_window_features.restype = None
+    L.or_window_features.argtypes = [P, P, C.c_int, C.c_double, C.c_double, C.c_double, P]
 
 
 def _p(a):
@@ -196,11 +204,16 @@ def bin_hits(g, n_events, layer_offsets, hit_pos, n_phi=64, n_eta=16):
 
 
 def build(g, prob, max_cands=6, mode=1, chi2_cut=30.0, n_phi=64, n_eta=16, window_margin=0.01, seeds=None,
-          hit_pos=None, hit_cov_full=None, seed_state=None, seed_cov=None):
+          hit_pos=None, hit_cov_full=None, seed_state=None, seed_cov=None, mlp_params=None, learned_nsigma=4.0):
     """Run the oracle builder on a synth.BuildProblem (optionally a subset of seeds).
+    mlp_params (4866 float64, or None for the plain window) selects the learned window.
 
     Returns dict of numpy arrays (see kf_oracle.h)."""
-    cfg = BuildCfg(max_cands, mode, chi2_cut, n_phi, n_eta, window_margin)
+    mp = None if mlp_params is None else _f64(mlp_params)
+    if mp is not None and mp.size != 4866:
+        raise ValueError("mlp_params must hold 4866 values")
+    cfg = BuildCfg(max_cands, mode, chi2_cut, n_phi, n_eta, window_margin, None if mp is None else mp.ctypes.data,
+                   learned_nsigma)
     L = g.n_layers
     E = prob.n_events
     hp = _f64(prob.hit_pos if hit_pos is None else hit_pos)
@@ -218,11 +231,37 @@ def build(g, prob, max_cands=6, mode=1, chi2_cut=30.0, n_phi=64, n_eta=16, windo
         n_cands=np.zeros(S, dtype=np.int32), cand_hits=np.zeros((S, N, L), dtype=np.int32),
         cand_chi2=np.zeros((S, N)), cand_nhits=np.zeros((S, N), dtype=np.int32),
         cand_status=np.zeros((S, N), dtype=np.int32), best_state=np.zeros((S, 6)), best_cov=np.zeros((S, 6, 6)),
-        margin_cut=np.zeros(S), margin_rank=np.zeros(S), hits_examined=np.zeros(S, dtype=np.int64))
+        margin_cut=np.zeros(S), margin_rank=np.zeros(S), hits_examined=np.zeros(S, dtype=np.int64),
+        margin_window=np.zeros(S), fallbacks=np.zeros(S, dtype=np.int64))
     rc = lib().or_build(C.byref(g), C.byref(cfg), E, _p(np.ascontiguousarray(prob.layer_hit_offsets, np.int64)),
                         _p(hp), _p(hc), S, _p(se), _p(ss), _p(sc), _p(sq), _p(sh), prob.first_layer,
                         _p(out["n_cands"]), _p(out["cand_hits"]), _p(out["cand_chi2"]), _p(out["cand_nhits"]),
                         _p(out["cand_status"]), _p(out["best_state"]), _p(out["best_cov"]), _p(out["margin_cut"]),
-                        _p(out["margin_rank"]), _p(out["hits_examined"]))
+                        _p(out["margin_rank"]), _p(out["hits_examined"]), _p(out["margin_window"]),
+                        _p(out["fallbacks"]))
     assert rc == 0
     return out
+
+
+def bf16(x):
+    return lib().or_bf16(float(x))
+
+
+def mlp_forward(params, X):
+    """Network outputs (n, 2) for features X (n, 8), device arithmetic semantics (see kf_oracle.h)."""
+    P = _f64(params)
+    X = _f64(X)
+    out = np.zeros((X.shape[0], 2))
+    o = np.zeros(2)
+    for i in range(X.shape[0]):
+        xi = np.ascontiguousarray(X[i])
+        lib().or_mlp_forward(_p(P), _p(xi), _p(o))
+        out[i] = o
+    return out
+
+
+def window_features(state, cov, q, r_from, r_to, zh):
+    """Features (8,) of one prediction (state (6,), cov (6,6))."""
+    f = np.zeros(8)
+    lib().or_window_features(_p(_f64(state)), _p(_f64(cov)), int(q), float(r_from), float(r_to), float(zh), _p(f))
+    return f

@@ -536,12 +536,103 @@ static double wrap_pi(double a) {
   return a;
 }
 
+/* ------------------------------------------------------------------------
+ * Learned search window (project addition).
+ * ---------------------------------------------------------------------- */
+double or_bf16(double x) {
+  /* nearest value with 8 significant bits (ties to even), bfloat16's exponent range */
+  if (!isfinite(x) || x == 0.0) return x;
+  int e;
+  frexp(x, &e); /* |x| = m 2^e, 0.5 <= m < 1 */
+  if (e < -125) e = -125;
+  double q = ldexp(1.0, e - 8);
+  return nearbyint(x / q) * q; /* default rounding mode: half to even */
+}
+
+/* the network on parameters already rounded (weights to bfloat16, biases to float32) */
+static void mlp_forward_rounded(const double* P, const double x[8], double o[2]) {
+  const double* W1 = P;
+  const double* b1 = W1 + 64 * 8;
+  const double* W2 = b1 + 64;
+  const double* b2 = W2 + 64 * 64;
+  const double* W3 = b2 + 64;
+  const double* b3 = W3 + 2 * 64;
+  double xb[8], h1[64], h2[64];
+  for (int i = 0; i < 8; ++i) xb[i] = or_bf16(x[i]);
+  for (int i = 0; i < 64; ++i) {
+    double a = b1[i];
+    for (int k = 0; k < 8; ++k) a += W1[i * 8 + k] * xb[k];
+    h1[i] = or_bf16(a > 0.0 ? a : 0.0);
+  }
+  for (int i = 0; i < 64; ++i) {
+    double a = b2[i];
+    for (int k = 0; k < 64; ++k) a += W2[i * 64 + k] * h1[k];
+    h2[i] = or_bf16(a > 0.0 ? a : 0.0);
+  }
+  for (int i = 0; i < 2; ++i) {
+    double a = b3[i];
+    for (int k = 0; k < 64; ++k) a += W3[i * 64 + k] * h2[k];
+    o[i] = a;
+  }
+}
+
+static void round_params(const double* P, double* R) {
+  /* weight blocks W1 [64][8], W2 [64][64], W3 [2][64] to bfloat16; biases to float32 */
+  static const int len[6] = {64 * 8, 64, 64 * 64, 64, 2 * 64, 2};
+  int off = 0;
+  for (int b = 0; b < 6; ++b) {
+    for (int i = 0; i < len[b]; ++i) R[off + i] = (b % 2 == 0) ? or_bf16(P[off + i]) : (double)(float)P[off + i];
+    off += len[b];
+  }
+}
+
+void or_mlp_forward(const double* P, const double x[8], double o[2]) {
+  double R[OR_MLP_PARAMS];
+  round_params(P, R);
+  mlp_forward_rounded(R, x, o);
+}
+
+void or_window_features(const double s[6], const double C[36], int q, double r_from, double r_to, double zh,
+                        double f[8]) {
+  double pt = hypot(s[3], s[4]);
+  double r = hypot(s[0], s[1]);
+  double tx = -s[1] / r, ty = s[0] / r;
+  double ctt = tx * tx * C[0] + 2.0 * tx * ty * C[1] + ty * ty * C[7];
+  f[0] = q / pt;
+  f[1] = s[5] / pt;
+  f[2] = s[2] / zh;
+  f[3] = (s[0] * s[4] - s[1] * s[3]) / (pt * r);
+  f[4] = r_from / 100.0;
+  f[5] = r_to / 100.0;
+  f[6] = 0.5 * log(ctt > 1e-30 ? ctt : 1e-30);
+  f[7] = 0.5 * log(C[14] > 1e-30 ? C[14] : 1e-30);
+}
+
+typedef struct {
+  int64_t hit;
+  double chi2;
+  int inside; /* inside the learned box */
+} ohit;
+
+typedef struct {
+  ohit* v;
+  int64_t n, cap;
+} hitvec;
+
+static void push_hit(hitvec* hv, ohit h) {
+  if (hv->n == hv->cap) {
+    hv->cap = hv->cap ? 2 * hv->cap : 64;
+    hv->v = (ohit*)realloc(hv->v, sizeof(ohit) * hv->cap);
+  }
+  hv->v[hv->n++] = h;
+}
+
 int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events, const int64_t* layer_offsets,
                  const double* hit_pos, const double* hit_cov, int64_t n_seeds, const int64_t* seed_event,
                  const double* seed_state, const double* seed_cov, const int8_t* seed_q, const int64_t* seed_hits,
                  int32_t first_layer, int32_t* n_cands, int32_t* cand_hits, double* cand_chi2, int32_t* cand_nhits,
                  int32_t* cand_status, double* best_state, double* best_cov, double* margin_cut,
-                 double* margin_rank, int64_t* hits_examined) {
+                 double* margin_rank, int64_t* hits_examined, double* margin_window, int64_t* fallbacks) {
   const int L = g->n_layers;
   const int N = cfg->max_cands;
   if (N < 1 || first_layer < 0 || n_seeds < 0) return -1;
@@ -575,11 +666,18 @@ int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events
     prop[k].hits = NULL;
   }
   childvec cv = {NULL, 0, 0};
+  hitvec hv = {NULL, 0, 0};
+  const int learned = cfg->mlp_params != NULL;
+  double* mlp_r = NULL;
+  if (learned) {
+    mlp_r = (double*)malloc(sizeof(double) * OR_MLP_PARAMS);
+    round_params(cfg->mlp_params, mlp_r);
+  }
 
   for (int64_t si = 0; si < n_seeds; ++si) {
     int64_t ev = seed_event[si];
-    double mcut = INFINITY, mrank = INFINITY;
-    int64_t examined = 0;
+    double mcut = INFINITY, mrank = INFINITY, mwin = INFINITY;
+    int64_t examined = 0, n_fb = 0;
     int nc = 1;
     memcpy(cur[0].s, seed_state + 6 * si, sizeof cur[0].s);
     memcpy(cur[0].C, seed_cov + 36 * si, sizeof cur[0].C);
@@ -634,8 +732,8 @@ int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events
             double mc = fabs(c2 - cut) / cut;
             if (mc < mcut) mcut = mc;
             if (c2 < cut) {
-              ochild ch = {c, h, pc->nhits + 1, pc->chi2 + c2};
-              push_child(&cv, ch);
+              ohit oh = {h, c2, 1};
+              push_hit(&hv, oh);
             }
           }
         } else {
@@ -673,12 +771,40 @@ int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events
                 double mc = fabs(c2 - cut) / cut;
                 if (mc < mcut) mcut = mc;
                 if (c2 < cut) {
-                  ochild ch = {c, h, pc->nhits + 1, pc->chi2 + c2};
-                  push_child(&cv, ch);
+                  ohit oh = {h, c2, 1};
+                  push_hit(&hv, oh);
                 }
               }
             }
         }
+        /* learned window: keep the compatible hits inside the learned box, if any */
+        int any_inside = 1;
+        if (learned) {
+          double f[8], o[2];
+          or_window_features(pp->s, pp->C, seed_q[si], l >= 1 ? g->r[l - 1] : 0.0, R, g->z_half[l], f);
+          mlp_forward_rounded(mlp_r, f, o);
+          double wl_t = cfg->learned_nsigma * exp(o[0]), wl_z = cfg->learned_nsigma * exp(o[1]);
+          double rr = hypot(pp->s[0], pp->s[1]);
+          double tx = -pp->s[1] / rr, ty = pp->s[0] / rr;
+          any_inside = 0;
+          for (int64_t i = 0; i < hv.n; ++i) {
+            const double* m = hit_pos + 3 * hv.v[i].hit;
+            double qt = fabs(tx * (m[0] - pp->s[0]) + ty * (m[1] - pp->s[1])) / wl_t;
+            double qz = fabs(m[2] - pp->s[2]) / wl_z;
+            double q = qt > qz ? qt : qz;
+            hv.v[i].inside = q <= 1.0;
+            any_inside |= hv.v[i].inside;
+            double mw = fabs(q - 1.0);
+            if (mw < mwin) mwin = mw;
+          }
+          if (!any_inside && hv.n > 0) n_fb++;
+        }
+        for (int64_t i = 0; i < hv.n; ++i)
+          if (hv.v[i].inside || !any_inside) {
+            ochild ch = {c, hv.v[i].hit, pc->nhits + 1, pc->chi2 + hv.v[i].chi2};
+            push_child(&cv, ch);
+          }
+        hv.n = 0;
         /* hole: the candidate crosses the layer without a hit */
         ochild hole = {c, -1, pc->nhits, pc->chi2};
         push_child(&cv, hole);
@@ -732,11 +858,15 @@ int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events
     if (margin_cut) margin_cut[si] = mcut;
     if (margin_rank) margin_rank[si] = mrank;
     if (hits_examined) hits_examined[si] = examined;
+    if (margin_window) margin_window[si] = mwin;
+    if (fallbacks) fallbacks[si] = n_fb;
   }
   for (int k = 0; k < N; ++k) {
     free(cur[k].hits);
     free(nxt[k].hits);
   }
+  free(hv.v);
+  free(mlp_r);
   free(cur);
   free(nxt);
   free(prop);

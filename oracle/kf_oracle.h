@@ -89,14 +89,23 @@ int32_t or_bin_hits(const or_geometry* g, int64_t n_events, const int64_t* layer
  * best_cov [S][36], margin_cut[S] (smallest relative distance of any decision
  * quantity from its threshold), margin_rank[S] (smallest relative chi2 gap
  * between rank-adjacent equal-nhits children near the cut-off),
- * hits_examined[S] (chi2 evaluations).  All output pointers but n_cands and
- * cand_hits are nullable. */
+ * hits_examined[S] (chi2 evaluations), margin_window[S] (learned window:
+ * smallest relative distance of a compatible hit from the learned box edge),
+ * fallbacks[S] (candidate-layers with compatible hits, none of them inside
+ * the learned window).  All output pointers but n_cands and cand_hits are nullable. */
 typedef struct {
   int32_t max_cands;
   int32_t mode;
   double chi2_cut;
   int32_t n_phi, n_eta;
   double window_margin; /* relative safety margin on the window half-widths */
+  /* learned search window (project addition, NULL = plain): network
+   * parameters (OR_MLP_PARAMS values, see or_mlp_forward) and the half widths
+   * in units of its scales.  A candidate's compatible hits must then also lie
+   * within nsigma s_t along the tangential direction and nsigma s_z in z of
+   * its prediction; when no hit does, the plain definition applies. */
+  const double* mlp_params;
+  double learned_nsigma;
 } or_build_cfg;
 
 int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events, const int64_t* layer_offsets,
@@ -104,7 +113,21 @@ int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events
                  const double* seed_state, const double* seed_cov, const int8_t* seed_q, const int64_t* seed_hits,
                  int32_t first_layer, int32_t* n_cands, int32_t* cand_hits, double* cand_chi2, int32_t* cand_nhits,
                  int32_t* cand_status, double* best_state, double* best_cov, double* margin_cut,
-                 double* margin_rank, int64_t* hits_examined);
+                 double* margin_rank, int64_t* hits_examined, double* margin_window, int64_t* fallbacks);
+
+/* Search-window network 8 -> 64 -> 64 -> 2 with ReLU hidden layers, as the
+ * device evaluates it: weights, inputs and hidden activations rounded to
+ * bfloat16 (or_bf16), biases to float32, sums in double precision.
+ * params: W1 [64][8], b1 [64], W2 [64][64], b2 [64], W3 [2][64], b3 [2]. */
+#define OR_MLP_PARAMS 4866
+double or_bf16(double x);
+void or_mlp_forward(const double* params, const double x[8], double o[2]);
+/* Features of a prediction (state, 6x6 covariance) crossing from radius
+ * r_from to r_to (z half length zh): q/pT, cot(theta), z/zh, sin of the angle
+ * between the transverse momentum and the radial direction, r_from/100,
+ * r_to/100, log of the tangential and z standard deviations. */
+void or_window_features(const double s[6], const double C[36], int q, double r_from, double r_to, double zh,
+                        double f[8]);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,7 @@
 #include <cstring>
 
 #include "kf_internal.hpp"
+#include "kf_mlp_device.hpp"
 
 using namespace kfd;
 
@@ -198,6 +199,8 @@ struct BuildP {
   float* best_cov;
   unsigned long long* counters;
   int32_t* queue;
+  const unsigned char* mlp;  // packed search-window network, or null for the plain window
+  float nsigma;
   Geom g;
 };
 
@@ -241,7 +244,7 @@ __device__ __forceinline__ float wrap_pi(float a) {
   return a;
 }
 
-template <int G, typename T>
+template <int G, typename T, bool LW>
 __device__ void build_tile(const BuildP& p, int64_t tile) {
   constexpr int SPW = 64 / G;  // seeds per wave
   const int lane = threadIdx.x & 63;
@@ -279,7 +282,8 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
   T chi2 = T(0);
   int nhits = 3;
   int nc = seed_ok ? 1 : 0;  // candidates of this seed (same in all its lanes)
-  uint64_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0;
+  uint64_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0, n_fb = 0;
+  const float qf = seed_ok ? static_cast<float>(p.seed_charge[s]) : 1.f;
   const float4* recs = reinterpret_cast<const float4*>(p.binned);
 
   for (int l = p.first_layer; l < L; ++l) {
@@ -304,6 +308,24 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
       }
       n_steps++;
     }
+    // ---- learned window: one network evaluation per candidate, all lanes of the wave together
+    float lwt = INFINITY, lwz = INFINITY;
+    if (LW) {
+      const bool use = active && pstat == 0;
+      float f[8];
+      if (use) {
+        window_features(ps, pc, qf, p.g.r[l - 1], p.g.r[l], p.g.z_half[l], f);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) f[k] = 0.f;
+      }
+      float o0, o1;
+      kfm::eval_wave(p.mlp, f, lane, o0, o1);
+      if (use) {
+        lwt = p.nsigma * __expf(o0);
+        lwz = p.nsigma * __expf(o1);
+      }
+    }
     // ---- scan the window's bins, keep the best N children of this candidate
     T lkey[G];
     int32_t lidx[G], lslot[G];
@@ -322,68 +344,78 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
       const float rtt = float(lp.att) + p.layer_vmax[2 * el];
       const float rzz = float(pc[5]) + p.layer_vmax[2 * el + 1];
       const float fac = 1.f + p.margin;
-      const float wt = sqrtf(p.chi2_cut * rtt) * fac;
-      const float wz = sqrtf(p.chi2_cut * rzz) * fac;
-      const float sphi = wt / R;
-      int ip0 = 0, nspan = p.n_phi;
-      if (sphi < 1.f) {
-        const float dphi = asinf(sphi);
-        if (dphi < 1.5707963f) {
-          const float php = atan2f(py0, px0);
-          ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
-          const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
-          nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
-        }
-      }
+      // plain half widths bound the chi2 < cut region (Cauchy-Schwarz on R^-1)
+      const float wt_plain = sqrtf(p.chi2_cut * rtt) * fac;
+      const float wz_plain = sqrtf(p.chi2_cut * rzz) * fac;
+      const float php = atan2f(py0, px0);
       const float emax = asinhf(p.g.z_half[l] / R);
-      const int ie0 = eta_bin_f(pz0 - wz, R, emax, p.n_eta);
-      const int ie1 = eta_bin_f(pz0 + wz, R, emax, p.n_eta);
       const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
-      for (int ie = ie0; ie <= ie1; ++ie) {
-        const int row = ie * p.n_phi;
-        const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
-        const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
-        for (int seg = 0; seg < 2; ++seg) {
-          int j0, j1;
-          if (seg == 0) {
-            j0 = bo[row + ip0];
-            j1 = bo[row + first_end];
-          } else {
-            if (wrap_end <= 0) break;
-            j0 = bo[row];
-            j1 = bo[row + wrap_end];
+      // pass 0: learned box (when it is tighter); pass 1: the plain window
+      for (int pass = (lwt < wt_plain || lwz < wz_plain) ? 0 : 1; pass < 2; ++pass) {
+        const float wt = pass == 0 ? fminf(lwt, wt_plain) : wt_plain;
+        const float wz = pass == 0 ? fminf(lwz, wz_plain) : wz_plain;
+        const float sphi = wt / R;
+        int ip0 = 0, nspan = p.n_phi;
+        if (sphi < 1.f) {
+          const float dphi = asinf(sphi);
+          if (dphi < 1.5707963f) {
+            ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
+            const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
+            nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
           }
-          for (int j = j0; j < j1; ++j) {
-            const float4 h = recs[static_cast<int64_t>(j) * 3];
-            const float dx = h.x - px0, dy = h.y - py0, dz = h.z - pz0;
-            n_box++;
-            if (fabsf(tx * dx + ty * dy) > wt || fabsf(dz) > wz) continue;
-            const float4 c0 = recs[static_cast<int64_t>(j) * 3 + 1];
-            const float4 c1 = recs[static_cast<int64_t>(j) * 3 + 2];
-            const float m[3] = {h.x, h.y, h.z};
-            const float v[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
-            T c2;
-            n_chi2++;
-            if (chi2_on_layer(ps, lp, m, v, c2)) continue;
-            if (!(c2 < T(p.chi2_cut))) continue;
-            n_comp++;
-            T nk = chi2 + (c2 > T(0) ? c2 : T(0));
-            int32_t ni = __float_as_int(h.w);
-            int32_t nj = j;
-#pragma unroll
-            for (int t = 0; t < G; ++t) {
-              const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
-              const T tk = lkey[t];
-              const int32_t ti = lidx[t], tj = lslot[t];
-              lkey[t] = sw ? nk : tk;
-              lidx[t] = sw ? ni : ti;
-              lslot[t] = sw ? nj : tj;
-              nk = sw ? tk : nk;
-              ni = sw ? ti : ni;
-              nj = sw ? tj : nj;
+        }
+        const int ie0 = eta_bin_f(pz0 - wz, R, emax, p.n_eta);
+        const int ie1 = eta_bin_f(pz0 + wz, R, emax, p.n_eta);
+        for (int ie = ie0; ie <= ie1; ++ie) {
+          const int row = ie * p.n_phi;
+          const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
+          const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
+          for (int seg = 0; seg < 2; ++seg) {
+            int j0, j1;
+            if (seg == 0) {
+              j0 = bo[row + ip0];
+              j1 = bo[row + first_end];
+            } else {
+              if (wrap_end <= 0) break;
+              j0 = bo[row];
+              j1 = bo[row + wrap_end];
             }
-            cnt = cnt + 1 < N ? cnt + 1 : N;
+            for (int j = j0; j < j1; ++j) {
+              const float4 h = recs[static_cast<int64_t>(j) * 3];
+              const float dx = h.x - px0, dy = h.y - py0, dz = h.z - pz0;
+              n_box++;
+              if (fabsf(tx * dx + ty * dy) > wt || fabsf(dz) > wz) continue;
+              const float4 c0 = recs[static_cast<int64_t>(j) * 3 + 1];
+              const float4 c1 = recs[static_cast<int64_t>(j) * 3 + 2];
+              const float m[3] = {h.x, h.y, h.z};
+              const float v[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
+              T c2;
+              n_chi2++;
+              if (chi2_on_layer(ps, lp, m, v, c2)) continue;
+              if (!(c2 < T(p.chi2_cut))) continue;
+              n_comp++;
+              T nk = chi2 + (c2 > T(0) ? c2 : T(0));
+              int32_t ni = __float_as_int(h.w);
+              int32_t nj = j;
+#pragma unroll
+              for (int t = 0; t < G; ++t) {
+                const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
+                const T tk = lkey[t];
+                const int32_t ti = lidx[t], tj = lslot[t];
+                lkey[t] = sw ? nk : tk;
+                lidx[t] = sw ? ni : ti;
+                lslot[t] = sw ? nj : tj;
+                nk = sw ? tk : nk;
+                ni = sw ? ti : ni;
+                nj = sw ? tj : nj;
+              }
+              cnt = cnt + 1 < N ? cnt + 1 : N;
+            }
           }
+        }
+        if (pass == 0) {
+          if (cnt > 0) break;
+          n_fb++;  // no hit in the learned window: the plain window decides
         }
       }
     }
@@ -494,7 +526,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
     }
   }
   if (p.counters) {
-    uint64_t v[KF_BUILD_COUNTERS] = {n_box, n_chi2, n_comp, n_steps, n_upd};
+    uint64_t v[KF_BUILD_COUNTERS] = {n_box, n_chi2, n_comp, n_steps, n_upd, n_fb};
 #pragma unroll
     for (int i = 0; i < KF_BUILD_COUNTERS; ++i) {
       uint64_t x = v[i];
@@ -505,13 +537,13 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
   }
 }
 
-template <int G, typename T>
+template <int G, typename T, bool LW>
 __global__ void __launch_bounds__(256) build_tiled_kernel(BuildP p) {
   const int64_t tile = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  build_tile<G, T>(p, tile);
+  build_tile<G, T, LW>(p, tile);
 }
 
-template <int G, typename T>
+template <int G, typename T, bool LW>
 __global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t n_tiles) {
   const int lane = threadIdx.x & 63;
   for (;;) {
@@ -519,7 +551,7 @@ __global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t
     if (lane == 0) t = atomicAdd(p.queue, 1);
     t = __shfl(t, 0);
     if (t >= n_tiles) break;
-    build_tile<G, T>(p, t);
+    build_tile<G, T, LW>(p, t);
   }
 }
 
@@ -529,6 +561,39 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
 }
 
 int lanes_for(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8; }
+
+struct Launch {
+  bool persistent, f64, learned;
+  unsigned grid, block;
+  hipStream_t stream;
+  int64_t n_tiles;
+};
+
+template <int G, typename T, bool LW>
+void launch_build(const Launch& c, const BuildP& p) {
+  if (c.persistent)
+    build_persistent_kernel<G, T, LW><<<c.grid, c.block, 0, c.stream>>>(p, c.n_tiles);
+  else
+    build_tiled_kernel<G, T, LW><<<c.grid, c.block, 0, c.stream>>>(p);
+}
+
+template <int G>
+void launch_g(const Launch& c, const BuildP& p) {
+  if (c.f64) {
+    if (c.learned) launch_build<G, double, true>(c, p); else launch_build<G, double, false>(c, p);
+  } else {
+    if (c.learned) launch_build<G, float, true>(c, p); else launch_build<G, float, false>(c, p);
+  }
+}
+
+void launch_any(int G, const Launch& c, const BuildP& p) {
+  switch (G) {
+    case 1: launch_g<1>(c, p); break;
+    case 2: launch_g<2>(c, p); break;
+    case 4: launch_g<4>(c, p); break;
+    default: launch_g<8>(c, p); break;
+  }
+}
 
 }  // namespace
 
@@ -579,7 +644,13 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   if (!(cfg->window_margin >= 0.f)) return set_error(KF_ERR_INVALID_ARG, "window_margin must be >= 0");
   if (cfg->mode != KF_BUILD_TILED && cfg->mode != KF_BUILD_PERSISTENT)
     return set_error(KF_ERR_INVALID_ARG, "unknown mode %d", cfg->mode);
-  if (cfg->window_mode != KF_WINDOW_PLAIN) return set_error(KF_ERR_INVALID_ARG, "window mode not available");
+  if (cfg->window_mode != KF_WINDOW_PLAIN && cfg->window_mode != KF_WINDOW_LEARNED)
+    return set_error(KF_ERR_INVALID_ARG, "unknown window mode %d", cfg->window_mode);
+  if (cfg->window_mode == KF_WINDOW_LEARNED) {
+    if (!(cfg->learned_nsigma > 0.f) || !std::isfinite(cfg->learned_nsigma))
+      return set_error(KF_ERR_INVALID_ARG, "learned_nsigma must be > 0");
+    if (!a->mlp_packed) return set_error(KF_ERR_INVALID_ARG, "learned window without mlp_packed");
+  }
   if (cfg->precision != KF_PREC_F32 && cfg->precision != KF_PREC_F64)
     return set_error(KF_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
   if (a->n_events < 0 || a->n_seeds < 0 || a->ld_seed < a->n_seeds)
@@ -623,6 +694,8 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   p.best_cov = a->best_cov;
   p.counters = reinterpret_cast<unsigned long long*>(a->counters);
   p.queue = nullptr;
+  p.mlp = cfg->window_mode == KF_WINDOW_LEARNED ? static_cast<const unsigned char*>(a->mlp_packed) : nullptr;
+  p.nsigma = cfg->learned_nsigma;
   p.g = ctx->dgeom;
   const int G = lanes_for(cfg->max_cands);
   const int64_t spw = 64 / G;
@@ -631,19 +704,16 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   if (wpb > 4) return set_error(KF_ERR_INVALID_ARG, "waves_per_block must be 1..4");
   hipStream_t stream = kfh::stream_of(a->stream);
   const bool f64 = cfg->precision == KF_PREC_F64;
+  Launch lc;
+  lc.f64 = f64;
+  lc.learned = p.mlp != nullptr;
+  lc.stream = stream;
+  lc.n_tiles = n_tiles;
+  lc.block = 64u * wpb;
   if (cfg->mode == KF_BUILD_TILED) {
-    const unsigned grid = static_cast<unsigned>((n_tiles + wpb - 1) / wpb);
-    const unsigned block = 64u * wpb;
-    switch (G * 2 + (f64 ? 1 : 0)) {
-      case 2: build_tiled_kernel<1, float><<<grid, block, 0, stream>>>(p); break;
-      case 3: build_tiled_kernel<1, double><<<grid, block, 0, stream>>>(p); break;
-      case 4: build_tiled_kernel<2, float><<<grid, block, 0, stream>>>(p); break;
-      case 5: build_tiled_kernel<2, double><<<grid, block, 0, stream>>>(p); break;
-      case 8: build_tiled_kernel<4, float><<<grid, block, 0, stream>>>(p); break;
-      case 9: build_tiled_kernel<4, double><<<grid, block, 0, stream>>>(p); break;
-      case 16: build_tiled_kernel<8, float><<<grid, block, 0, stream>>>(p); break;
-      default: build_tiled_kernel<8, double><<<grid, block, 0, stream>>>(p); break;
-    }
+    lc.persistent = false;
+    lc.grid = static_cast<unsigned>((n_tiles + wpb - 1) / wpb);
+    launch_any(G, lc, p);
     return kfh::check_hip(hipGetLastError(), "build_tiled_kernel launch");
   }
   if (!a->workspace || a->workspace_bytes < kf_build_workspace_size(cfg, a->n_seeds))
@@ -651,18 +721,9 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   p.queue = static_cast<int32_t*>(a->workspace);
   fill_i32_kernel<<<1, 64, 0, stream>>>(p.queue, 1, 0);
   const int bpc = cfg->blocks_per_cu > 0 ? cfg->blocks_per_cu : 2;
-  const unsigned grid = static_cast<unsigned>(ctx->num_cus * bpc);
-  const unsigned block = 64u * wpb;
-  switch (G * 2 + (f64 ? 1 : 0)) {
-    case 2: build_persistent_kernel<1, float><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    case 3: build_persistent_kernel<1, double><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    case 4: build_persistent_kernel<2, float><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    case 5: build_persistent_kernel<2, double><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    case 8: build_persistent_kernel<4, float><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    case 9: build_persistent_kernel<4, double><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    case 16: build_persistent_kernel<8, float><<<grid, block, 0, stream>>>(p, n_tiles); break;
-    default: build_persistent_kernel<8, double><<<grid, block, 0, stream>>>(p, n_tiles); break;
-  }
+  lc.persistent = true;
+  lc.grid = static_cast<unsigned>(ctx->num_cus * bpc);
+  launch_any(G, lc, p);
   return kfh::check_hip(hipGetLastError(), "build_persistent_kernel launch");
 }
 

@@ -482,4 +482,27 @@ KF_DEV int32_t update_on_layer(T s[6], T c[21], const float m[3], const float v[
   return 0;
 }
 
+// Features of a prediction for the learned search window, in this order:
+// q/pT, cot(theta), z/z_half, sin of the angle between the transverse momentum
+// and the radial direction, r_from/100, r_to/100, and the logs of the
+// predicted position's tangential and z standard deviations (cm).
+template <typename T>
+__device__ __forceinline__ void window_features(const T s[6], const T c[21], float q, float r_from, float r_to,
+                                                float zh, float f[8]) {
+  const float x = float(s[0]), y = float(s[1]), z = float(s[2]), px = float(s[3]), py = float(s[4]),
+              pz = float(s[5]);
+  const float ipt = __frsqrt_rn(px * px + py * py);
+  const float ir = __frsqrt_rn(x * x + y * y);
+  const float tx = -y * ir, ty = x * ir;  // tangential unit vector
+  const float ctt = tx * tx * float(c[0]) + 2.f * tx * ty * float(c[1]) + ty * ty * float(c[2]);
+  f[0] = q * ipt;
+  f[1] = pz * ipt;
+  f[2] = z / zh;
+  f[3] = (x * py - y * px) * ipt * ir;
+  f[4] = r_from * 0.01f;
+  f[5] = r_to * 0.01f;
+  f[6] = 0.5f * logf(fmaxf(ctt, 1e-30f));
+  f[7] = 0.5f * logf(fmaxf(float(c[5]), 1e-30f));
+}
+
 }  // namespace kfd

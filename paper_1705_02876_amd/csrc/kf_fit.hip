@@ -86,34 +86,21 @@ __global__ void __launch_bounds__(256) update_kernel(int64_t n, int64_t ld, floa
   status[i] = st;
 }
 
-// Features of a prediction for the learned search window (see kfmi.h):
-// q/pT, cot(theta), z/z_half, sin(phi_dir - phi_pos), r_from/100, r_to/100,
-// log sigma_rphi, log sigma_z of the predicted position; targets are the
-// tangential and z offsets of the track's own hit from the prediction.
+// Training record of a prediction for the learned search window: its
+// features, then the tangential and z offsets of the track's own hit.
 template <typename T>
 __device__ __forceinline__ void emit_residual(float* __restrict__ out, int64_t ldr, int64_t row, const T s[6],
                                               const T c[21], float q, float r_from, float r_to, float zh,
                                               const float m[3]) {
-  const float x = float(s[0]), y = float(s[1]), z = float(s[2]), px = float(s[3]), py = float(s[4]),
-              pz = float(s[5]);
-  const float ipt = __frsqrt_rn(px * px + py * py);
+  float f[KF_RES_FEATURES];
+  window_features(s, c, q, r_from, r_to, zh, f);
+  const float x = float(s[0]), y = float(s[1]), z = float(s[2]);
   const float ir = __frsqrt_rn(x * x + y * y);
-  const float tx = -y * ir, ty = x * ir;  // tangential unit vector
-  const float ctt = tx * tx * float(c[0]) + 2.f * tx * ty * float(c[1]) + ty * ty * float(c[2]);
-  const float f[KF_RES_FEATURES + 2] = {
-      q * ipt,
-      pz * ipt,
-      z / zh,
-      (x * py - y * px) * ipt * ir,
-      r_from * 0.01f,
-      r_to * 0.01f,
-      0.5f * logf(fmaxf(ctt, 1e-30f)),
-      0.5f * logf(fmaxf(float(c[5]), 1e-30f)),
-      tx * (m[0] - x) + ty * (m[1] - y),
-      m[2] - z,
-  };
+  const float tx = -y * ir, ty = x * ir;
 #pragma unroll
-  for (int k = 0; k < KF_RES_FEATURES + 2; ++k) out[k * ldr + row] = f[k];
+  for (int k = 0; k < KF_RES_FEATURES; ++k) out[k * ldr + row] = f[k];
+  out[KF_RES_FEATURES * ldr + row] = tx * (m[0] - x) + ty * (m[1] - y);
+  out[(KF_RES_FEATURES + 1) * ldr + row] = m[2] - z;
 }
 
 template <typename T>

@@ -16,59 +16,14 @@
 #include <cmath>
 
 #include "kf_internal.hpp"
+#include "kf_mlp_device.hpp"
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kIn = 8, kH = 64, kOut = 2;
-constexpr int kOffW1 = 0;                            // W1 [64][8]
-constexpr int kOffB1 = kOffW1 + kH * kIn;            // 512
-constexpr int kOffW2 = kOffB1 + kH;                  // 576
-constexpr int kOffB2 = kOffW2 + kH * kH;             // 4672
-constexpr int kOffW3 = kOffB2 + kH;                  // 4736
-constexpr int kOffB3 = kOffW3 + kOut * kH;           // 4864
-static_assert(kOffB3 + kOut == KF_MLP_PARAMS, "parameter count");
-
-// packed buffer: bf16 tiles of 64 lanes x 4 values (512 bytes each), then biases
-constexpr int kTileBytes = 512;
-constexpr int kPkW1 = 0;                        // 4 tiles   (rows 16mt.., k = input 0..15, 8..15 zero)
-constexpr int kPkW2 = kPkW1 + 4 * kTileBytes;   // 16 tiles  (mt, kt)
-constexpr int kPkW3 = kPkW2 + 16 * kTileBytes;  // 4 tiles   (rows = outputs 0..15, 2..15 zero; kt)
-constexpr int kPkW2T = kPkW3 + 4 * kTileBytes;  // 16 tiles  (W2^T: rows = inputs, k = outputs)
-constexpr int kPkW3T = kPkW2T + 16 * kTileBytes;  // 4 tiles (W3^T: rows = hidden 16mt.., k = outputs 0..15)
-constexpr int kPkB1 = kPkW3T + 4 * kTileBytes;  // float b1[64]
-constexpr int kPkB2 = kPkB1 + 4 * kH;
-constexpr int kPkB3 = kPkB2 + 4 * kH;
-static_assert(kPkB3 + 4 * kOut == KF_MLP_PACKED_BYTES, "packed size");
+using namespace kfm;
 
 constexpr int kGradWaves = 1024;
 constexpr int kPartial = KF_MLP_PARAMS + 2;  // + loss, count
-
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7F800000u) == 0x7F800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
-  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-  return static_cast<uint16_t>(u >> 16);
-}
-
-__device__ __forceinline__ bf16x4 to_bf16x4(f32x4 v) {
-  bf16x4 r;
-  r[0] = static_cast<short>(f2bf(v[0]));
-  r[1] = static_cast<short>(f2bf(v[1]));
-  r[2] = static_cast<short>(f2bf(v[2]));
-  r[3] = static_cast<short>(f2bf(v[3]));
-  return r;
-}
-
-__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ bf16x4 load_tile(const unsigned char* packed, int off, int t, int lane) {
-  return reinterpret_cast<const bf16x4*>(packed + off + t * kTileBytes)[lane];
-}
 
 // parameter feeding element e of lane `lane` in tile t of each packed block
 __device__ float packed_source(const float* P, int block, int t, int lane, int e) {
@@ -108,65 +63,6 @@ __global__ void __launch_bounds__(256) pack_kernel(const float* __restrict__ P, 
     float* fb = reinterpret_cast<float*>(packed + kPkB1);
     fb[j] = j < kH ? P[kOffB1 + j] : (j < 2 * kH ? P[kOffB2 + j - kH] : P[kOffB3 + j - 2 * kH]);
   }
-}
-
-struct FwdWeights {
-  bf16x4 w1[4], w2[16], w3[4];
-  f32x4 b1[4], b2[4], b3;
-};
-
-__device__ __forceinline__ void load_fwd(const unsigned char* packed, int lane, FwdWeights& W) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t) W.w1[t] = load_tile(packed, kPkW1, t, lane);
-#pragma unroll
-  for (int t = 0; t < 16; ++t) W.w2[t] = load_tile(packed, kPkW2, t, lane);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) W.w3[t] = load_tile(packed, kPkW3, t, lane);
-  const float* fb1 = reinterpret_cast<const float*>(packed + kPkB1);
-  const float* fb2 = reinterpret_cast<const float*>(packed + kPkB2);
-  const float* fb3 = reinterpret_cast<const float*>(packed + kPkB3);
-  const int q = 4 * (lane >> 4);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      W.b1[mt][e] = fb1[16 * mt + q + e];
-      W.b2[mt][e] = fb2[16 * mt + q + e];
-    }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) W.b3[e] = (q + e < kOut) ? fb3[q + e] : 0.f;
-}
-
-// Forward pass of one 16-record tile.  xb: B operand (lane l: record l%16,
-// features 4(l/16)..+3, zero beyond 8).  Returns the output tile (lanes 0..15:
-// elements 0, 1 = log s_t, log s_z of record l) and keeps the hidden tiles.
-__device__ __forceinline__ f32x4 forward_tile(const FwdWeights& W, bf16x4 xb, f32x4 h1[4], f32x4 h2[4],
-                                              bf16x4 h1b[4], bf16x4 h2b[4]) {
-  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 a = mfma(W.w1[mt], xb, z);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) a[e] = fmaxf(a[e] + W.b1[mt][e], 0.f);
-    h1[mt] = a;
-    h1b[mt] = to_bf16x4(a);
-  }
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 a = z;
-#pragma unroll
-    for (int kt = 0; kt < 4; ++kt) a = mfma(W.w2[mt * 4 + kt], h1b[kt], a);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) a[e] = fmaxf(a[e] + W.b2[mt][e], 0.f);
-    h2[mt] = a;
-    h2b[mt] = to_bf16x4(a);
-  }
-  f32x4 o = z;
-#pragma unroll
-  for (int kt = 0; kt < 4; ++kt) o = mfma(W.w3[kt], h2b[kt], o);
-#pragma unroll
-  for (int e = 0; e < 4; ++e) o[e] += W.b3[e];
-  return o;
 }
 
 __device__ __forceinline__ bf16x4 load_x_tile(const float* __restrict__ x, int64_t ldx, int64_t rec, bool valid,

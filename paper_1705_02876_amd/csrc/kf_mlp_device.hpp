@@ -1,0 +1,163 @@
+// kf_mlp_device.hpp -- device side of the search-window network 8 -> 64 -> 64 -> 2
+// (ReLU) on the bf16 matrix cores, shared by the training kernels and the
+// track builder.
+//
+// Products run in the orientation features x records with
+// v_mfma_f32_16x16x16_bf16: a 16-record tile is the N dimension, the weights
+// are the A operand (bf16 tiles, pre-arranged by the pack kernel), the
+// activations the B operand.  Register layouts of that instruction (64 lanes):
+//   A[i][k]: lane i + 16 (k / 4), element k % 4
+//   B[k][j]: lane j + 16 (k / 4), element k % 4
+//   D[i][j]: lane j + 16 (i / 4), element i % 4
+// so the accumulator tile of one layer is the B operand of the next and the
+// forward pass moves no data between layers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kfmi.h"
+
+namespace kfm {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kIn = 8, kH = 64, kOut = 2;
+constexpr int kOffW1 = 0;                            // W1 [64][8]
+constexpr int kOffB1 = kOffW1 + kH * kIn;            // 512
+constexpr int kOffW2 = kOffB1 + kH;                  // 576
+constexpr int kOffB2 = kOffW2 + kH * kH;             // 4672
+constexpr int kOffW3 = kOffB2 + kH;                  // 4736
+constexpr int kOffB3 = kOffW3 + kOut * kH;           // 4864
+static_assert(kOffB3 + kOut == KF_MLP_PARAMS, "parameter count");
+
+// packed buffer: bf16 tiles of 64 lanes x 4 values (512 bytes each), then biases
+constexpr int kTileBytes = 512;
+constexpr int kPkW1 = 0;                        // 4 tiles   (rows 16mt.., k = input 0..15, 8..15 zero)
+constexpr int kPkW2 = kPkW1 + 4 * kTileBytes;   // 16 tiles  (mt, kt)
+constexpr int kPkW3 = kPkW2 + 16 * kTileBytes;  // 4 tiles   (rows = outputs 0..15, 2..15 zero; kt)
+constexpr int kPkW2T = kPkW3 + 4 * kTileBytes;  // 16 tiles  (W2^T: rows = inputs, k = outputs)
+constexpr int kPkW3T = kPkW2T + 16 * kTileBytes;  // 4 tiles (W3^T: rows = hidden 16mt.., k = outputs 0..15)
+constexpr int kPkB1 = kPkW3T + 4 * kTileBytes;  // float b1[64]
+constexpr int kPkB2 = kPkB1 + 4 * kH;
+constexpr int kPkB3 = kPkB2 + 4 * kH;
+static_assert(kPkB3 + 4 * kOut == KF_MLP_PACKED_BYTES, "packed size");
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return static_cast<uint16_t>(u >> 16);
+}
+
+__device__ __forceinline__ bf16x4 to_bf16x4(f32x4 v) {
+  bf16x4 r;
+  r[0] = static_cast<short>(f2bf(v[0]));
+  r[1] = static_cast<short>(f2bf(v[1]));
+  r[2] = static_cast<short>(f2bf(v[2]));
+  r[3] = static_cast<short>(f2bf(v[3]));
+  return r;
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x4 load_tile(const unsigned char* packed, int off, int t, int lane) {
+  return reinterpret_cast<const bf16x4*>(packed + off + t * kTileBytes)[lane];
+}
+
+struct FwdWeights {
+  bf16x4 w1[4], w2[16], w3[4];
+  f32x4 b1[4], b2[4], b3;
+};
+
+__device__ __forceinline__ void load_fwd(const unsigned char* packed, int lane, FwdWeights& W) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) W.w1[t] = load_tile(packed, kPkW1, t, lane);
+#pragma unroll
+  for (int t = 0; t < 16; ++t) W.w2[t] = load_tile(packed, kPkW2, t, lane);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) W.w3[t] = load_tile(packed, kPkW3, t, lane);
+  const float* fb1 = reinterpret_cast<const float*>(packed + kPkB1);
+  const float* fb2 = reinterpret_cast<const float*>(packed + kPkB2);
+  const float* fb3 = reinterpret_cast<const float*>(packed + kPkB3);
+  const int q = 4 * (lane >> 4);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      W.b1[mt][e] = fb1[16 * mt + q + e];
+      W.b2[mt][e] = fb2[16 * mt + q + e];
+    }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) W.b3[e] = (q + e < kOut) ? fb3[q + e] : 0.f;
+}
+
+// Forward pass of one 16-record tile.  xb: B operand (lane l: record l%16,
+// features 4(l/16)..+3, zero beyond 8).  Returns the output tile (lanes 0..15:
+// elements 0, 1 = log s_t, log s_z of record l) and keeps the hidden tiles.
+__device__ __forceinline__ f32x4 forward_tile(const FwdWeights& W, bf16x4 xb, f32x4 h1[4], f32x4 h2[4],
+                                              bf16x4 h1b[4], bf16x4 h2b[4]) {
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 a = mfma(W.w1[mt], xb, z);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = fmaxf(a[e] + W.b1[mt][e], 0.f);
+    h1[mt] = a;
+    h1b[mt] = to_bf16x4(a);
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 a = z;
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) a = mfma(W.w2[mt * 4 + kt], h1b[kt], a);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = fmaxf(a[e] + W.b2[mt][e], 0.f);
+    h2[mt] = a;
+    h2b[mt] = to_bf16x4(a);
+  }
+  f32x4 o = z;
+#pragma unroll
+  for (int kt = 0; kt < 4; ++kt) o = mfma(W.w3[kt], h2b[kt], o);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) o[e] += W.b3[e];
+  return o;
+}
+
+// One prediction per lane (64 records): features f[8] in, (log s_t, log s_z)
+// out.  Must be called by all 64 lanes of the wave together (wave-uniform
+// control flow); lanes without a record pass zeros and ignore the result.
+__device__ __forceinline__ void eval_wave(const unsigned char* packed, const float f[kIn], int lane, float& o0,
+                                          float& o1) {
+  FwdWeights W;
+  load_fwd(packed, lane, W);
+  const int g = lane >> 4;
+  o0 = 0.f;
+  o1 = 0.f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int src = 16 * t + (lane & 15);
+    f32x4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float lo = __shfl(f[e], src);
+      const float hi = __shfl(f[4 + e], src);
+      v[e] = g == 0 ? lo : (g == 1 ? hi : 0.f);
+    }
+    f32x4 h1[4], h2[4];
+    bf16x4 h1b[4], h2b[4];
+    const f32x4 o = forward_tile(W, to_bf16x4(v), h1, h2, h1b, h2b);
+    // lanes 0..15 hold the outputs of records 16 t + lane
+    const float r0 = __shfl(o[0], lane & 15);
+    const float r1 = __shfl(o[1], lane & 15);
+    if (g == t) {
+      o0 = r0;
+      o1 = r1;
+    }
+  }
+}
+
+}  // namespace kfm

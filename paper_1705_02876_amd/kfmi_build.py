@@ -7,6 +7,7 @@ BINNED_FLOATS = 12
 BUILD_TILED, BUILD_PERSISTENT = 0, 1
 WINDOW_PLAIN, WINDOW_LEARNED = 0, 1
 PREC_F32, PREC_F64 = 0, 1
+BUILD_COUNTERS = 6  # box tests, chi2 evaluations, compatible hits, candidate-layer steps, updates, fallbacks
 
 
 class kf_bin_args(C.Structure):
@@ -23,6 +24,7 @@ class kf_build_cfg(C.Structure):
         ("max_cands", C.c_int32), ("chi2_cut", C.c_float), ("n_phi", C.c_int32), ("n_eta", C.c_int32),
         ("window_margin", C.c_float), ("mode", C.c_int32), ("window_mode", C.c_int32),
         ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("precision", C.c_int32),
+        ("learned_nsigma", C.c_float),
     ]
 
 
@@ -35,7 +37,7 @@ class kf_build_args(C.Structure):
         ("n_cands", C.c_void_p), ("cand_hits", C.c_void_p), ("cand_chi2", C.c_void_p),
         ("cand_nhits", C.c_void_p), ("cand_status", C.c_void_p), ("best_state", C.c_void_p),
         ("best_cov", C.c_void_p), ("counters", C.c_void_p), ("workspace", C.c_void_p),
-        ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
+        ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p), ("mlp_packed", C.c_void_p),
     ]
 
 
@@ -98,13 +100,13 @@ def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16,
 
 
 def make_cfg(max_cands=6, chi2_cut=30.0, n_phi=64, n_eta=16, window_margin=0.01, mode=BUILD_TILED,
-             window_mode=WINDOW_PLAIN, waves_per_block=0, blocks_per_cu=0, precision=PREC_F64):
+             window_mode=WINDOW_PLAIN, waves_per_block=0, blocks_per_cu=0, precision=PREC_F64, learned_nsigma=4.0):
     return kf_build_cfg(max_cands, chi2_cut, n_phi, n_eta, window_margin, mode, window_mode, waves_per_block,
-                        blocks_per_cu, precision)
+                        blocks_per_cu, precision, learned_nsigma)
 
 
 def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=None, counters=None, workspace=None,
-          stream=None):
+          stream=None, mlp_packed=None):
     """kf_build.  seeds: dict(offsets int64 (E+1), state (6,ld), cov (21,ld), charge int8 (S), hits int32 (3,ld), n).
 
     Returns dict of device tensors (n_cands, cand_hits (L,S,N), cand_chi2 (S,N), cand_nhits, cand_status,
@@ -142,7 +144,13 @@ def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=Non
     a.n_cands, a.cand_hits, a.cand_chi2 = _ptr(out["n_cands"]), _ptr(out["cand_hits"]), _ptr(out["cand_chi2"])
     a.cand_nhits, a.cand_status = _ptr(out["cand_nhits"]), _ptr(out["cand_status"])
     a.best_state, a.best_cov = _ptr(out.get("best_state")), _ptr(out.get("best_cov"))
+    if counters is not None and (counters.dtype != torch.int64 or counters.numel() < BUILD_COUNTERS):
+        raise ValueError(f"counters must hold {BUILD_COUNTERS} int64")
     a.counters = _ptr(counters)
+    if cfg.window_mode == WINDOW_LEARNED:
+        if mlp_packed is None or mlp_packed.dtype != torch.uint8 or mlp_packed.numel() < 23048:
+            raise ValueError("the learned window needs the packed network (uint8, 23048 bytes)")
+        a.mlp_packed = _ptr(mlp_packed)
     if workspace is not None:
         a.workspace, a.workspace_bytes = _ptr(workspace), workspace.numel()
     a.stream = kfmi._stream(stream)

@@ -18,6 +18,12 @@ from kfutil import check_chi2, check_params, rounded
 pytestmark = pytest.mark.gpu
 
 STABLE = 1e-3
+# learned window: the device network's output (a log scale) differs from the
+# oracle's by float32 against float64 sums and rare bfloat16 rounding flips of
+# inputs and activations (at most 4e-3 in a float32 emulation of the device
+# sums); a hit whose box coordinate is within 1% of the
+# learned edge is not a stable decision.
+WSTABLE = 1e-2
 
 
 @pytest.fixture(scope="module")
@@ -30,15 +36,19 @@ def ctx():
     c.close()
 
 
-def _gpu_build(ctx, prob, N=6, mode=0, det32=None, counters=False, precision=1):
+def _gpu_build(ctx, prob, N=6, mode=0, det32=None, counters=False, precision=1, mlp=None, nsigma=4.0):
     import torch
-    from paper_1705_02876_amd import kfmi_build as KB
+    from paper_1705_02876_amd import kfmi_build as KB, kfmi_mlp as M
     ctx.kf_set_geometry(det32)
     seeds, hits = KB.upload_problem(prob)
     bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events)
-    cfg = KB.make_cfg(max_cands=N, mode=mode, precision=precision)
-    cnt = torch.zeros(5, dtype=torch.int64, device="cuda") if counters else None
-    out = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, counters=cnt)
+    packed = None
+    if mlp is not None:
+        packed = M.pack(ctx, torch.from_numpy(np.asarray(mlp, np.float32)).cuda(), M.new_packed())
+    cfg = KB.make_cfg(max_cands=N, mode=mode, precision=precision,
+                      window_mode=KB.WINDOW_PLAIN if mlp is None else KB.WINDOW_LEARNED, learned_nsigma=nsigma)
+    cnt = torch.zeros(KB.BUILD_COUNTERS, dtype=torch.int64, device="cuda") if counters else None
+    out = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, counters=cnt, mlp_packed=packed)
     torch.cuda.synchronize()
     S_ = seeds["n"]
     res = dict(n_cands=out["n_cands"].cpu().numpy()[:S_],
@@ -52,18 +62,19 @@ def _gpu_build(ctx, prob, N=6, mode=0, det32=None, counters=False, precision=1):
     return res, bins
 
 
-def _oracle_build(orc, prob, det32, N=6, seeds=None):
+def _oracle_build(orc, prob, det32, N=6, seeds=None, mlp=None, nsigma=4.0):
     g = orc.geometry(det32)
     return orc.build(g, prob, max_cands=N, mode=1, hit_pos=rounded(prob.hit_pos),
                      hit_cov_full=S.unpack3(rounded(prob.hit_cov)), seed_state=rounded(prob.seed_state),
-                     seed_cov=S.unpack6(rounded(S.pack6(prob.seed_cov))), seeds=seeds)
+                     seed_cov=S.unpack6(rounded(S.pack6(prob.seed_cov))), seeds=seeds,
+                     mlp_params=None if mlp is None else rounded(mlp), learned_nsigma=float(np.float32(nsigma)))
 
 
-def _compare(gpu, ora, sel=None, label=""):
+def _compare(gpu, ora, sel=None, label="", min_same=0.97):
     """Exact candidate lists on stable seeds; returns (n_stable, n_all, n_match_all)."""
     n = ora["n_cands"].shape[0]
     g = {k: (v if sel is None else v[sel]) for k, v in gpu.items() if k != "counters"}
-    stable = (ora["margin_cut"] > STABLE) & (ora["margin_rank"] > STABLE)
+    stable = (ora["margin_cut"] > STABLE) & (ora["margin_rank"] > STABLE) & (ora["margin_window"] > WSTABLE)
     same = (g["n_cands"] == ora["n_cands"]) & np.all(g["cand_hits"] == ora["cand_hits"], axis=(1, 2)) & np.all(
         g["cand_nhits"] == ora["cand_nhits"], axis=1)
     bad = np.nonzero(stable & ~same)[0]
@@ -76,7 +87,7 @@ def _compare(gpu, ora, sel=None, label=""):
         check_chi2(g["cand_chi2"][live, k], ora["cand_chi2"][live, k], f"cand chi2 rank {k}")
     live = ok & (ora["cand_status"][:, 0] == 0)
     check_params(g["best_state"][live], ora["best_state"][live], "best state")
-    assert same.mean() > 0.97, same.mean()
+    assert same.mean() > min_same, same.mean()
     return stable.sum(), n, same.sum()
 
 
@@ -188,3 +199,47 @@ def test_build_full_size_sampled(ctx, orc, precision):
         ordered = (nh[live, k] > nh[live, k + 1]) | ((nh[live, k] == nh[live, k + 1]) & (c2[live, k] <= c2[live, k + 1]))
         assert ordered.all()
     print(f"[build full-size] counters box/chi2/compatible/steps/updates = {gpu['counters']}", flush=True)
+
+
+def _window_net(b3, w3_scale=0.1, seed=21):
+    from oracle import mlp
+    p = mlp.init(seed)
+    p["b1"] = np.random.Generator(np.random.PCG64(seed + 1)).normal(0, 0.05, 64)
+    p["W3"] *= w3_scale
+    p["b3"] = np.asarray(b3, np.float64)
+    return mlp.flatten(p)
+
+
+@pytest.mark.parametrize("N,mode,precision", [(6, 1, 1), (1, 0, 0), (4, 0, 1)])
+def test_learned_window_limits_equal_plain(ctx, N, mode, precision):
+    """A network whose window holds every compatible hit, and one whose window holds none
+    (every candidate falls back), both give the plain build exactly."""
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = S.make_build_problem([900, 1400], det, 66)
+    plain, _ = _gpu_build(ctx, prob, N=N, mode=mode, det32=det32, precision=precision, counters=True)
+    for b3, label in (([20.0, 20.0], "huge"), ([-40.0, -40.0], "tiny")):
+        lw, _ = _gpu_build(ctx, prob, N=N, mode=mode, det32=det32, precision=precision, counters=True,
+                           mlp=_window_net(b3, 0.0))
+        print(f"[learned limits {label} N={N}] counters {lw['counters']}", flush=True)
+        for k in plain:
+            if k != "counters":
+                assert np.array_equal(plain[k], lw[k], equal_nan=True), (label, k)
+        assert lw["counters"][5] == 0 if label == "huge" else lw["counters"][5] > 0
+
+
+@pytest.mark.parametrize("N,mode,precision", [(6, 1, 1), (6, 0, 0), (1, 0, 1), (8, 1, 0)])
+def test_learned_window_parity(ctx, orc, N, mode, precision):
+    """A network with candidate-dependent windows of about three hit sigmas against the
+    oracle's learned build (same network, bfloat16 device semantics)."""
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = S.make_build_problem([800, 1500, 3, 1200], det, 67)
+    net = _window_net([np.log(0.012), np.log(0.11)])
+    gpu, _ = _gpu_build(ctx, prob, N=N, mode=mode, det32=det32, precision=precision, mlp=net, nsigma=3.0,
+                        counters=True)
+    ora = _oracle_build(orc, prob, det32, N=N, mlp=net, nsigma=3.0)
+    print(f"[learned parity N={N}] oracle fallbacks {ora['fallbacks'].sum()}, device fallback passes "
+          f"{gpu['counters'][5]}, window-stable seeds {(ora['margin_window'] > WSTABLE).mean():.3f}", flush=True)
+    assert ora["fallbacks"].sum() > 0
+    _compare(gpu, ora, label=f"learned N={N} mode={mode} precision={precision}", min_same=0.9)
