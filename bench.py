@@ -141,6 +141,53 @@ def cpu_baseline_build(prob, det32, max_seeds=300_000, N=6):
                       f"build N={N}, {cores} host threads (each bins the sample's hits), {dt:.2f} s wall"}
 
 
+def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, plain_build_ms):
+    """Learned search window: residual records of the fit, full-batch training on the GPU, then the
+    learned build timed like the plain one and both judged against the simulation truth."""
+    import torch
+    from paper_1705_02876_amd import judge, kfmi_build as KB, window
+    stream = torch.cuda.current_stream()
+    E = lambda: torch.cuda.Event(enable_timing=True)
+    x, t = window.fit_records(ctx, fit_dev, det.n_layers)
+    n_rec = x.shape[1]
+    torch.cuda.synchronize()
+    t0, t1 = E(), E()
+    t0.record(stream)
+    tr = window.train(ctx, x, t, steps=args.train_steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    train_ms = t0.elapsed_time(t1)
+    lcfg = KB.make_cfg(max_cands=N, mode=cfg.mode, precision=cfg.precision, window_mode=KB.WINDOW_LEARNED,
+                       learned_nsigma=args.nsigma)
+    lout = KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, mlp_packed=tr.packed)
+    cnt = torch.zeros(KB.BUILD_COUNTERS, dtype=torch.int64, device="cuda")
+    KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=lout, counters=cnt,
+             mlp_packed=tr.packed)
+    for _ in range(args.warmup):
+        KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=lout, mlp_packed=tr.packed)
+    torch.cuda.synchronize()
+    evs = [(E(), E()) for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(stream)
+        KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=lout, mlp_packed=tr.packed)
+        b.record(stream)
+    torch.cuda.synchronize()
+    lms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    S_ = seeds["n"]
+    e_plain = judge.judge_problem(bp, bout["cand_hits"][:, :S_, 0].T.cpu().numpy())
+    e_learn = judge.judge_problem(bp, lout["cand_hits"][:, :S_, 0].T.cpu().numpy())
+    c = cnt.cpu().numpy()
+    return {"nsigma": args.nsigma, "build_ms": lms, "plain_build_ms": plain_build_ms,
+            "speedup_vs_plain": plain_build_ms / lms, "seeds_built_per_s_build_only": S_ / (lms * 1e-3),
+            "eff_plain": e_plain["eff"], "eff_learned": e_learn["eff"],
+            "eff_loss_pp": 100.0 * (e_plain["eff"] - e_learn["eff"]),
+            "fake_rate_plain": e_plain["fake_rate"], "fake_rate_learned": e_learn["fake_rate"],
+            "counters": {"box_tests": int(c[0]), "chi2_evals": int(c[1]), "compatible": int(c[2]),
+                         "cand_layer_steps": int(c[3]), "updates": int(c[4]), "fallback_passes": int(c[5])},
+            "train_records": int(n_rec), "train_tracks": int(fit_dev["n"]), "train_steps": args.train_steps,
+            "train_ms": train_ms, "train_ms_per_step": train_ms / max(args.train_steps, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +199,10 @@ def main():
     ap.add_argument("--build-mode", choices=["tiled", "persistent"], default="persistent")
     ap.add_argument("--build-precision", choices=["f32", "f64"], default="f64")
     ap.add_argument("--fit-fp64", action="store_true", help="double-precision registers in the fit")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-window leg")
+    ap.add_argument("--nsigma", type=float, default=4.0, help="learned window half width in network scales")
+    ap.add_argument("--train-tracks", type=int, default=625_000, help="fit tracks whose residuals train the window")
+    ap.add_argument("--train-steps", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -288,6 +339,10 @@ def main():
                            "updates": int(counters[4])},
         "fit_status_nonzero": int((stat != 0).sum().item()),
     }
+    if not args.no_learned:
+        out["learned_window"] = learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N,
+                                            dict(state=st_in, cov=cv_in, q=q, hidx=hidx, hpos=hpos, hcov=hcov,
+                                                 n=min(args.train_tracks, n)), build_ms)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_fit(fp, det32)
         out["cpu_baseline_build"] = cpu_baseline_build(bp, det32)

@@ -15,35 +15,35 @@ def efficiency(best_hits, seed_track, seed_event, hit_track, track_nhits, min_ma
     A seed's simulated track counts if it has >= min_match hits; it is found if
     the seed's best candidate has >= min_match hits from that track and they are
     >= frac of the candidate's hits.  A best candidate is a fake if its most
-    frequent sim track contributes >= min_match hits but < frac of its hits, or
-    if it is matched to no track with >= min_match hits while having >=
-    min_match hits itself; otherwise (fewer than min_match matched) neither.
+    frequent sim track contributes >= min_match hits but < frac of its hits;
+    candidates whose most frequent track contributes fewer than min_match hits
+    are neither found nor fake.
     Returns dict(eff, fake_rate, n_eligible, n_found, n_fake, n_judged).
     """
+    best_hits = np.asarray(best_hits)
     S = best_hits.shape[0]
-    n_elig = n_found = n_fake = n_judged = 0
-    for s in range(S):
-        h = best_hits[s]
-        h = h[h >= 0]
-        trk = hit_track[h] if h.size else np.zeros(0, dtype=np.int64)
-        own = seed_track[s]
-        ntrue = track_nhits[seed_event[s]][own]
-        nm_own = int((trk == own).sum())
-        ok_own = nm_own >= min_match and nm_own >= frac * h.size
-        if ntrue >= min_match:
-            n_elig += 1
-            n_found += int(ok_own)
-        # fake / neither classification by the candidate's dominant sim track
-        real = trk[trk >= 0]
-        if real.size:
-            vals, cnt = np.unique(real, return_counts=True)
-            nm = int(cnt.max())
-        else:
-            nm = 0
-        if nm >= min_match:
-            n_judged += 1
-            if nm < frac * h.size:
-                n_fake += 1
+    if S == 0:
+        return dict(eff=0.0, fake_rate=0.0, n_eligible=0, n_found=0, n_fake=0, n_judged=0)
+    valid = best_hits >= 0
+    trk = np.where(valid, np.asarray(hit_track)[np.where(valid, best_hits, 0)], -1)  # (S, L), -1 = none/noise
+    own = np.asarray(seed_track)
+    ev = np.asarray(seed_event)
+    sizes = np.array([len(t) for t in track_nhits], dtype=np.int64)
+    start = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    ntrue = np.concatenate([np.asarray(t) for t in track_nhits])[start[ev] + own]
+    nh = valid.sum(axis=1)
+    nm_own = ((trk == own[:, None]) & valid).sum(axis=1)
+    found = (nm_own >= min_match) & (nm_own >= frac * nh)
+    elig = ntrue >= min_match
+    # hits of each candidate's most frequent sim track (noise excluded)
+    nm = np.zeros(S, dtype=np.int64)
+    for j in range(trk.shape[1]):
+        cj = ((trk == trk[:, j:j + 1]) & (trk[:, j:j + 1] >= 0)).sum(axis=1)
+        nm = np.maximum(nm, cj)
+    judged = nm >= min_match
+    fake = judged & (nm < frac * nh)
+    n_elig, n_found = int(elig.sum()), int((elig & found).sum())
+    n_judged, n_fake = int(judged.sum()), int(fake.sum())
     return dict(eff=n_found / max(n_elig, 1), fake_rate=n_fake / max(n_judged, 1), n_eligible=n_elig,
                 n_found=n_found, n_fake=n_fake, n_judged=n_judged)
 
