@@ -319,6 +319,41 @@ int32_t kf_mlp_grad(kf_ctx* ctx, int64_t n, const float* x, int64_t ldx, const f
 int32_t kf_mlp_adam(kf_ctx* ctx, float* params, const float* grad, float* m, float* v, int32_t step, float lr,
                     float beta1, float beta2, float eps, void* packed, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Runtime: graph capture and launch autotuning.
+ *
+ * The paper attributes part of its GPU time to kernel launches and to a
+ * single event not filling the device (Sec. 4.2, 4.3).  A graph replays a
+ * captured sequence of calls with one launch; the autotuner picks the build
+ * launch shape for a problem size.
+ *
+ * kf_graph_begin starts capturing on `stream` (a created stream, not the
+ * default one); every kf_* call issued on that stream by this thread until
+ * kf_graph_end is recorded instead of run (arguments, pointers and the
+ * geometry are frozen at capture time; none of the captured calls allocates
+ * or clears memory with a memset).  A begun capture must always be ended,
+ * also after a failed call.  kf_graph_launch replays the graph on any stream.
+ * kf_graph_destroy releases it. */
+typedef struct kf_graph kf_graph;
+int32_t kf_graph_begin(kf_ctx* ctx, void* stream);
+int32_t kf_graph_end(kf_ctx* ctx, void* stream, kf_graph** out);
+int32_t kf_graph_launch(kf_graph* graph, void* stream);
+void kf_graph_destroy(kf_graph* graph);
+
+/* kf_build_autotune: synchronous.  Times kf_build (cfg as given, args as
+ * given, counters ignored) over the launch shapes {tiled, persistent} x
+ * waves_per_block {1, 2, 4} x blocks_per_cu {1, 2, 4, 8} (persistent only if
+ * args carries a workspace), `reps` timed runs each after one warm-up, and
+ * writes the fastest mode / waves_per_block / blocks_per_cu into *cfg and its
+ * average time into *best_ms (nullable).  The outputs in args are
+ * overwritten like by any build.  Results are cached in the context per
+ * (max_cands, precision, window_mode, power-of-two bucket of n_seeds, bins);
+ * a cached entry is returned without timing.  kf_autotune_save / _load
+ * write and read the cache as one JSON object per line. */
+int32_t kf_build_autotune(kf_ctx* ctx, kf_build_cfg* cfg, const kf_build_args* args, int32_t reps, float* best_ms);
+int32_t kf_autotune_save(kf_ctx* ctx, const char* path);
+int32_t kf_autotune_load(kf_ctx* ctx, const char* path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,10 +6,17 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <map>
 #include <string>
 
 #include "../../include/kfmi.h"
 #include "kf_device.hpp"
+
+// one autotuned build launch configuration
+struct kf_tuned {
+  int32_t mode = 0, waves_per_block = 0, blocks_per_cu = 0;
+  float ms = 0.f;
+};
 
 struct kf_ctx {
   int device = 0;
@@ -17,6 +24,7 @@ struct kf_ctx {
   kf_geometry geom{};
   kfd::Geom dgeom{};
   int num_cus = 0;
+  std::map<std::string, kf_tuned> tuned;  // autotune cache, key from kf_build_autotune
 };
 
 namespace kfh {

@@ -51,6 +51,20 @@ def declare(lib):
     lib.kf_build_workspace_size.argtypes = [P, I64]
     lib.kf_build.restype = I32
     lib.kf_build.argtypes = [P, P, P]
+    lib.kf_graph_begin.restype = I32
+    lib.kf_graph_begin.argtypes = [P, P]
+    lib.kf_graph_end.restype = I32
+    lib.kf_graph_end.argtypes = [P, P, C.POINTER(P)]
+    lib.kf_graph_launch.restype = I32
+    lib.kf_graph_launch.argtypes = [P, P]
+    lib.kf_graph_destroy.restype = None
+    lib.kf_graph_destroy.argtypes = [P]
+    lib.kf_build_autotune.restype = I32
+    lib.kf_build_autotune.argtypes = [P, P, P, I32, C.POINTER(C.c_float)]
+    lib.kf_autotune_save.restype = I32
+    lib.kf_autotune_save.argtypes = [P, C.c_char_p]
+    lib.kf_autotune_load.restype = I32
+    lib.kf_autotune_load.argtypes = [P, C.c_char_p]
     return lib
 
 
@@ -69,7 +83,7 @@ def check_offsets(t, count, limit, name):
 
 
 def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16, out=None, workspace=None,
-             stream=None):
+             stream=None, check=True):
     """kf_bin_hits.  Returns dict(bin_offsets, perm, binned, layer_vmax) of device tensors."""
     import torch
     from . import kfmi
@@ -77,7 +91,8 @@ def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16,
     ldh = hit_pos.shape[1]
     L = ctx.n_layers
     dev = hit_pos.device
-    check_offsets(layer_offsets, n_events * L, ldh, "layer_offsets")
+    if check:
+        check_offsets(layer_offsets, n_events * L, ldh, "layer_offsets")
     if out is None:
         out = dict(bin_offsets=torch.empty(n_events * L, n_phi * n_eta + 1, dtype=torch.int32, device=dev),
                    perm=torch.empty(max(ldh, 1), dtype=torch.int32, device=dev),
@@ -106,7 +121,7 @@ def make_cfg(max_cands=6, chi2_cut=30.0, n_phi=64, n_eta=16, window_margin=0.01,
 
 
 def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=None, counters=None, workspace=None,
-          stream=None, mlp_packed=None):
+          stream=None, mlp_packed=None, check=True):
     """kf_build.  seeds: dict(offsets int64 (E+1), state (6,ld), cov (21,ld), charge int8 (S), hits int32 (3,ld), n).
 
     Returns dict of device tensors (n_cands, cand_hits (L,S,N), cand_chi2 (S,N), cand_nhits, cand_status,
@@ -119,7 +134,7 @@ def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=Non
     N = cfg.max_cands
     L = ctx.n_layers
     dev = seeds["state"].device
-    if S > 0:
+    if S > 0 and check:  # host copies of the offsets: not allowed while a graph is being captured
         check_offsets(seeds["offsets"], n_events, S, "seed_offsets")
         if int(seeds["offsets"][n_events].item()) != S or int(seeds["offsets"][0].item()) != 0:
             raise ValueError("seed_offsets must start at 0 and end at n_seeds")
@@ -154,8 +169,80 @@ def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=Non
     if workspace is not None:
         a.workspace, a.workspace_bytes = _ptr(workspace), workspace.numel()
     a.stream = kfmi._stream(stream)
+    # kept for kf_build_autotune, with every tensor the pointers refer to
+    out["_args"] = a
+    out["_keep"] = (seeds, bins, layer_offsets, workspace, mlp_packed, counters)
     kfmi._check(lib.kf_build(ctx.h, C.byref(cfg), C.byref(a)))
     return out
+
+
+def autotune(ctx, cfg, out, reps=3):
+    """kf_build_autotune on the arguments of a previous build() call (its `out`): updates cfg in place and
+    returns the best average time in ms."""
+    from . import kfmi
+    ms = C.c_float(0.0)
+    kfmi._check(kfmi.load_library().kf_build_autotune(ctx.h, C.byref(cfg), C.byref(out["_args"]), int(reps),
+                                                      C.byref(ms)))
+    return ms.value
+
+
+def autotune_save(ctx, path):
+    from . import kfmi
+    kfmi._check(kfmi.load_library().kf_autotune_save(ctx.h, str(path).encode()))
+
+
+def autotune_load(ctx, path):
+    from . import kfmi
+    kfmi._check(kfmi.load_library().kf_autotune_load(ctx.h, str(path).encode()))
+
+
+class Graph:
+    """A HIP graph of library calls: capture(fn) records every kf_* call fn issues on a side stream;
+    launch() replays them."""
+
+    def __init__(self, ctx):
+        import torch
+        self.ctx = ctx
+        self.stream = torch.cuda.Stream()  # default priority
+        self.h = None
+
+    def capture(self, fn):
+        import torch
+        from . import kfmi
+        lib = kfmi.load_library()
+        torch.cuda.synchronize()
+        kfmi._check(lib.kf_graph_begin(self.ctx.h, C.c_void_p(self.stream.cuda_stream)))
+        err = None
+        try:
+            with torch.cuda.stream(self.stream):
+                fn()
+        except Exception as e:  # the capture must be ended in any case
+            err = e
+        h = C.c_void_p()
+        rc = lib.kf_graph_end(self.ctx.h, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if err is not None:
+            if h.value:
+                lib.kf_graph_destroy(h)
+            raise err
+        kfmi._check(rc)
+        self.h = h
+        return self
+
+    def launch(self, stream=None):
+        from . import kfmi
+        kfmi._check(kfmi.load_library().kf_graph_launch(self.h, kfmi._stream(stream)))
+
+    def close(self):
+        if self.h:
+            from . import kfmi
+            kfmi.load_library().kf_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def upload_problem(prob, dtype_note=None):
