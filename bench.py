@@ -41,6 +41,42 @@ def fit_bytes(n, L, n_hits_total):
     return n * (108 + 1 + 4 * L + 108 + 12) + 36 * n_hits_total
 
 
+KERNEL_SOURCES = {
+    "fit_kernel": ("kf_fit.hip", "kf_device.hpp", "kf_internal.hpp"),
+    "bin_kernel": ("kf_build.hip", "kf_device.hpp", "kf_internal.hpp"),
+    "build_persistent_kernel": ("kf_build.hip", "kf_device.hpp", "kf_mlp_device.hpp", "kf_internal.hpp"),
+    "build_tiled_kernel": ("kf_build.hip", "kf_device.hpp", "kf_mlp_device.hpp", "kf_internal.hpp"),
+}
+
+
+def source_digest(kernel):
+    """sha256 over the sources a kernel is compiled from (to tell whether profiled counters still apply)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1705_02876_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel
+    (profiles/<kernel>_traffic.md: FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), or None when
+    there is none or the kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256", "traffic_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != source_digest(kernel) or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def fit_flops(fp):
     has = fp.hit_idx >= 0
     last = fp.last_layer
@@ -203,6 +239,8 @@ def main():
     ap.add_argument("--nsigma", type=float, default=4.0, help="learned window half width in network scales")
     ap.add_argument("--train-tracks", type=int, default=625_000, help="fit tracks whose residuals train the window")
     ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB device copy first (calibrates HBM byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -222,6 +260,13 @@ def main():
     from paper_1705_02876_amd import kfmi, kfmi_build as KB
     ctx = kfmi.Context(0)
     ctx.kf_set_geometry(det32)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = fp.state0.shape[0]
     L = det.n_layers
     dev = "cuda"
@@ -304,10 +349,12 @@ def main():
     d = kern[dom]
     if d["alu_frac"] >= d["hbm_frac"]:
         roof = {"bound": "alu", "achieved": d["tflops"], "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": d["alu_frac"], "traffic": None}
+                "frac": d["alu_frac"]}
     else:
         roof = {"bound": "hbm", "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["hbm_frac"], "traffic": None}
+                "frac": d["hbm_frac"]}
+    roof["traffic"] = measured_traffic(dom)
+    roof["algorithmic_bytes"] = d["bytes"]
     roof["kernel"] = dom
     out = {
         "metric": METRIC,

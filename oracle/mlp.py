@@ -10,8 +10,12 @@ averaged over the batch; the optimiser is Adam (Kingma & Ba, 2015) with
 bias-corrected moments.  Parameters are kept in a dict of float64 arrays.
 
 round_bf16 is the bfloat16 format's definition (8 significant bits, round to
-nearest, ties to even), used to state the network as a device holds it: its
-weights in bfloat16.
+nearest, ties to even).  forward_device / grad_device state the network with
+the roundings of a bfloat16 matrix-core evaluation written out: weights,
+inputs and hidden activations are bfloat16 operands, the backward products
+take the output gradient and the pre-activation gradients as bfloat16
+operands, biases are float32, sums are exact (float64 here).  With every value
+representable in bfloat16 they coincide with forward / grad.
 """
 from __future__ import annotations
 
@@ -78,6 +82,38 @@ def forward(p, X):
     h2 = np.maximum(a2, 0.0)
     o = h2 @ p["W3"].T + p["b3"]
     return o, (a1, h1, a2, h2)
+
+
+def forward_device(p, X):
+    """Outputs (B, 2) and (a1, h1b, a2, h2b) of the network with bfloat16 operands (see module doc)."""
+    q = bf16_params(p)
+    xb = round_bf16(X)
+    a1 = xb @ q["W1"].T + q["b1"]
+    h1b = round_bf16(np.maximum(a1, 0.0))
+    a2 = h1b @ q["W2"].T + q["b2"]
+    h2b = round_bf16(np.maximum(a2, 0.0))
+    o = h2b @ q["W3"].T + q["b3"]
+    return o, (xb, a1, h1b, a2, h2b)
+
+
+def grad_device(p, X, T):
+    """Mean loss and gradient of the network with bfloat16 operands: the output gradient dO and the
+    pre-activation gradients dA2, dA1 enter the products as bfloat16; the bias gradients sum the unrounded
+    values."""
+    B = X.shape[0]
+    q = bf16_params(p)
+    o, (xb, a1, h1b, a2, h2b) = forward_device(p, X)
+    e = T * T * np.exp(-2.0 * o)
+    L = float(np.mean(np.sum(0.5 * e + o, axis=1)))
+    do = 1.0 - e
+    dob = round_bf16(do)
+    da2 = (dob @ q["W3"]) * (a2 > 0)
+    da2b = round_bf16(da2)
+    da1 = (da2b @ q["W2"]) * (a1 > 0)
+    da1b = round_bf16(da1)
+    g = {"W3": dob.T @ h2b / B, "b3": do.sum(axis=0) / B, "W2": da2b.T @ h1b / B, "b2": da2.sum(axis=0) / B,
+         "W1": da1b.T @ xb / B, "b1": da1.sum(axis=0) / B}
+    return L, g
 
 
 def loss(p, X, T):

@@ -21,12 +21,17 @@ def ctx():
     c.close()
 
 
+def _tensors(out):
+    """The output tensors of a binding result (build() also stores its call arguments under '_' keys)."""
+    return {k: v for k, v in out.items() if not k.startswith("_")}
+
+
 def _host(out):
-    return {k: v.cpu().numpy().copy() for k, v in out.items() if not k.startswith("_")}
+    return {k: v.cpu().numpy().copy() for k, v in _tensors(out).items()}
 
 
 def _empty_like_out(out):
-    return {k: v.clone() for k, v in out.items() if not k.startswith("_")}
+    return {k: v.clone() for k, v in _tensors(out).items()}
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -58,7 +63,7 @@ def test_graph_replays_bin_and_build(ctx, mode):
 
     g = KB.Graph(ctx).capture(step)
     for rep in range(4):
-        for v in list(bins_g.values()) + list(out_g.values()):
+        for v in list(_tensors(bins_g).values()) + list(_tensors(out_g).values()):
             v.fill_(-3)
         # unrelated eager work on the default stream between replays
         eager2 = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, workspace=wsb)

@@ -99,3 +99,45 @@ def test_bf16_rounding_definition():
     np.testing.assert_array_equal(mlp.round_bf16(y), y)
     _, e = np.frexp(y)
     np.testing.assert_array_equal(np.ldexp(np.round(np.ldexp(np.frexp(y)[0], 8)), e - 8), y)
+
+
+def _exact_params(seed):
+    """Dyadic weights and sparse W2 so that every operand of the network is a bfloat16 value."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    p = {"W1": r.integers(-2, 3, (64, 8)) * 0.5, "b1": r.integers(-2, 3, 64) * 1.0, "W2": np.zeros((64, 64)),
+         "b2": r.integers(-2, 3, 64) * 1.0, "W3": np.zeros((2, 64)), "b3": np.array([0.25, -0.5])}
+    for i in range(64):
+        p["W2"][i, r.choice(64, 2, replace=False)] = r.integers(-2, 3, 2) * 0.5
+    for k in range(2):
+        p["W3"][k, r.choice(64, 3, replace=False)] = r.integers(-2, 3, 3) * 0.25
+    return p
+
+
+def test_device_semantics_reduce_to_the_exact_network():
+    p = _exact_params(4)
+    X = np.random.Generator(np.random.PCG64(5)).integers(-4, 5, (300, 8)) * 0.5
+    # targets such that the output gradients are bfloat16 values: t^2 exp(-2 o) = 1 - dO exactly
+    o, _ = mlp.forward(p, X)
+    d = np.random.Generator(np.random.PCG64(6)).integers(-3, 1, o.shape) * 0.25
+    T = np.sqrt((1.0 - d) * np.exp(2.0 * o))
+    od, _ = mlp.forward_device(p, X)
+    np.testing.assert_array_equal(od, o)
+    L, g = mlp.grad(p, X, T)
+    Ld, gd = mlp.grad_device(p, X, T)
+    assert abs(L - Ld) < 1e-12
+    for k in g:
+        np.testing.assert_allclose(gd[k], g[k], rtol=1e-9, atol=1e-12)
+
+
+def test_device_semantics_close_to_the_exact_network():
+    # generic parameters: bfloat16 operands move the gradient by a few 2^-9 relative steps
+    x, t = S.window_records(21, 4000)
+    p = mlp.init(22)
+    s2 = np.mean(t * t, axis=0)
+    p["b3"] = 0.5 * np.log(s2)
+    p["W3"] *= 0.1
+    L, g = mlp.grad(p, x, t)
+    Ld, gd = mlp.grad_device(p, x, t)
+    assert abs(L - Ld) < 2e-2 * max(1.0, abs(L))
+    for k in g:
+        assert np.abs(gd[k] - g[k]).max() <= 5e-2 * np.abs(g[k]).max(), k
