@@ -29,6 +29,8 @@ constexpr int kBinWaves = 16;
 constexpr int kBinThreads = kBinWaves * 64;
 constexpr int kMaxBins = 2048;
 constexpr uint32_t kHole = 0xFFFFFFu;
+constexpr int kScanUnroll = 4;  // hit records box-tested per lane and scan iteration
+constexpr int kPendCap = 16;    // per-lane list of box-passing slots awaiting their chi2
 
 __device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, double zh, int n_phi, int n_eta) {
 #pragma clang fp contract(off)
@@ -284,6 +286,9 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
   int nc = seed_ok ? 1 : 0;  // candidates of this seed (same in all its lanes)
   uint64_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0, n_fb = 0;
   const float qf = seed_ok ? static_cast<float>(p.seed_charge[s]) : 1.f;
+  // per-wave pending lists, [slot][lane] so that a wave's accesses hit 64 consecutive words
+  __shared__ int32_t pend_all[4][kPendCap][64];
+  int32_t (*pend)[64] = pend_all[(threadIdx.x >> 6) & 3];
   const float4* recs = reinterpret_cast<const float4*>(p.binned);
 
   for (int l = p.first_layer; l < L; ++l) {
@@ -336,13 +341,15 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
       lslot[t] = 0;
     }
     int cnt = 0;
-    if (active && pstat == 0) {
+    {
+      // Window geometry of this lane's candidate (dead lanes get an empty scan).
+      const bool live = active && pstat == 0;
       const float R = p.g.r[l];
       const LocalPred<T> lp = local_pred(ps, pc);
       const float tx = float(lp.tx), ty = float(lp.ty);
       const float px0 = float(ps[0]), py0 = float(ps[1]), pz0 = float(ps[2]);
-      const float rtt = float(lp.att) + p.layer_vmax[2 * el];
-      const float rzz = float(pc[5]) + p.layer_vmax[2 * el + 1];
+      const float rtt = live ? float(lp.att) + p.layer_vmax[2 * el] : 0.f;
+      const float rzz = live ? float(pc[5]) + p.layer_vmax[2 * el + 1] : 0.f;
       const float fac = 1.f + p.margin;
       // plain half widths bound the chi2 < cut region (Cauchy-Schwarz on R^-1)
       const float wt_plain = sqrtf(p.chi2_cut * rtt) * fac;
@@ -350,72 +357,110 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
       const float php = atan2f(py0, px0);
       const float emax = asinhf(p.g.z_half[l] / R);
       const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
-      // pass 0: learned box (when it is tighter); pass 1: the plain window
-      for (int pass = (lwt < wt_plain || lwz < wz_plain) ? 0 : 1; pass < 2; ++pass) {
+      const bool tighter = live && (lwt < wt_plain || lwz < wz_plain);
+      // pass 0: learned box where it is tighter; pass 1: the plain window for every other live candidate
+      // and for those whose learned box held no compatible hit (fallback)
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool part = pass == 0 ? tighter : (live && (!tighter || cnt == 0));
+        if (pass == 1 && tighter && cnt == 0) n_fb++;
+        if (__ballot(part) == 0) continue;
         const float wt = pass == 0 ? fminf(lwt, wt_plain) : wt_plain;
         const float wz = pass == 0 ? fminf(lwz, wz_plain) : wz_plain;
-        const float sphi = wt / R;
-        int ip0 = 0, nspan = p.n_phi;
-        if (sphi < 1.f) {
-          const float dphi = asinf(sphi);
-          if (dphi < 1.5707963f) {
-            ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
-            const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
-            nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
+        int ip0 = 0, nspan = p.n_phi, ie0 = 0, ie1 = -1;
+        if (part) {
+          const float sphi = wt / R;
+          if (sphi < 1.f) {
+            const float dphi = asinf(sphi);
+            if (dphi < 1.5707963f) {
+              ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
+              const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
+              nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
+            }
           }
+          ie0 = eta_bin_f(pz0 - wz, R, emax, p.n_eta);
+          ie1 = eta_bin_f(pz0 + wz, R, emax, p.n_eta);
         }
-        const int ie0 = eta_bin_f(pz0 - wz, R, emax, p.n_eta);
-        const int ie1 = eta_bin_f(pz0 + wz, R, emax, p.n_eta);
-        for (int ie = ie0; ie <= ie1; ++ie) {
-          const int row = ie * p.n_phi;
-          const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
-          const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
-          for (int seg = 0; seg < 2; ++seg) {
-            int j0, j1;
-            if (seg == 0) {
-              j0 = bo[row + ip0];
-              j1 = bo[row + first_end];
+        const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
+        const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
+        // Slot ranges r = 0 .. rend-1: row ie0 + r/2, segment r%2 (the wrapped part of the phi span).
+        // The loop is wave-synchronous: every iteration box-tests up to 4 slots per lane with their loads
+        // issued together; slots that pass go to this lane's pending list in LDS, and whenever a list
+        // could overflow (and at the end) all lanes evaluate their pending chi2 in lockstep.
+        int r = 0;
+        const int rend = part ? 2 * (ie1 - ie0 + 1) : 0;
+        int j = 0, jend = 0, npend = 0;
+        for (;;) {
+          while (j >= jend && r < rend) {
+            const int row = (ie0 + (r >> 1)) * p.n_phi;
+            if ((r & 1) == 0) {
+              j = bo[row + ip0];
+              jend = bo[row + first_end];
+            } else if (wrap_end > 0) {
+              j = bo[row];
+              jend = bo[row + wrap_end];
             } else {
-              if (wrap_end <= 0) break;
-              j0 = bo[row];
-              j1 = bo[row + wrap_end];
+              j = jend = 0;
             }
-            for (int j = j0; j < j1; ++j) {
-              const float4 h = recs[static_cast<int64_t>(j) * 3];
-              const float dx = h.x - px0, dy = h.y - py0, dz = h.z - pz0;
-              n_box++;
-              if (fabsf(tx * dx + ty * dy) > wt || fabsf(dz) > wz) continue;
-              const float4 c0 = recs[static_cast<int64_t>(j) * 3 + 1];
-              const float4 c1 = recs[static_cast<int64_t>(j) * 3 + 2];
-              const float m[3] = {h.x, h.y, h.z};
-              const float v[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
-              T c2;
-              n_chi2++;
-              if (chi2_on_layer(ps, lp, m, v, c2)) continue;
-              if (!(c2 < T(p.chi2_cut))) continue;
-              n_comp++;
-              T nk = chi2 + (c2 > T(0) ? c2 : T(0));
-              int32_t ni = __float_as_int(h.w);
-              int32_t nj = j;
-#pragma unroll
-              for (int t = 0; t < G; ++t) {
-                const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
-                const T tk = lkey[t];
-                const int32_t ti = lidx[t], tj = lslot[t];
-                lkey[t] = sw ? nk : tk;
-                lidx[t] = sw ? ni : ti;
-                lslot[t] = sw ? nj : tj;
-                nk = sw ? tk : nk;
-                ni = sw ? ti : ni;
-                nj = sw ? tj : nj;
-              }
-              cnt = cnt + 1 < N ? cnt + 1 : N;
-            }
+            ++r;
           }
-        }
-        if (pass == 0) {
-          if (cnt > 0) break;
-          n_fb++;  // no hit in the learned window: the plain window decides
+          const bool has = j < jend;
+          const bool any = __ballot(has) != 0;
+          if (any && has) {
+            float4 hv[kScanUnroll];
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+              const int jc = (j + u < jend) ? j + u : jend - 1;
+              hv[u] = recs[static_cast<int64_t>(jc) * 3];
+            }
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+              if (j + u < jend) {
+                n_box++;
+                const float dx = hv[u].x - px0, dy = hv[u].y - py0, dz = hv[u].z - pz0;
+                if (fabsf(tx * dx + ty * dy) <= wt && fabsf(dz) <= wz) pend[npend++][lane] = j + u;
+              }
+            }
+            j = (j + kScanUnroll < jend) ? j + kScanUnroll : jend;
+          }
+          const bool last_round = !any;
+          if (last_round || __ballot(npend > kPendCap - kScanUnroll) != 0) {
+            int m = npend;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+            for (int k = 0; k < m; ++k) {
+              if (k < npend) {
+                const int js = pend[k][lane];
+                const float4 h = recs[static_cast<int64_t>(js) * 3];
+                const float4 c0 = recs[static_cast<int64_t>(js) * 3 + 1];
+                const float4 c1 = recs[static_cast<int64_t>(js) * 3 + 2];
+                const float mm[3] = {h.x, h.y, h.z};
+                const float vv[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
+                T c2;
+                n_chi2++;
+                if (!chi2_on_layer(ps, lp, mm, vv, c2) && c2 < T(p.chi2_cut)) {
+                  n_comp++;
+                  T nk = chi2 + (c2 > T(0) ? c2 : T(0));
+                  int32_t ni = __float_as_int(h.w);
+                  int32_t nj = js;
+#pragma unroll
+                  for (int t = 0; t < G; ++t) {
+                    const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
+                    const T tk = lkey[t];
+                    const int32_t ti = lidx[t], tj = lslot[t];
+                    lkey[t] = sw ? nk : tk;
+                    lidx[t] = sw ? ni : ti;
+                    lslot[t] = sw ? nj : tj;
+                    nk = sw ? tk : nk;
+                    ni = sw ? ti : ni;
+                    nj = sw ? tj : nj;
+                  }
+                  cnt = cnt + 1 < N ? cnt + 1 : N;
+                }
+              }
+            }
+            npend = 0;
+          }
+          if (last_round) break;
         }
       }
     }

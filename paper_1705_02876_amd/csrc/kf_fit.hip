@@ -103,6 +103,14 @@ __device__ __forceinline__ void emit_residual(float* __restrict__ out, int64_t l
   out[(KF_RES_FEATURES + 1) * ldr + row] = m[2] - z;
 }
 
+__device__ __forceinline__ void load_hit(const float* __restrict__ hit_pos, const float* __restrict__ hit_cov,
+                                         int64_t ldh, int32_t h, float m[3], float v[6]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m[k] = hit_pos[k * ldh + h];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = hit_cov[k * ldh + h];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const float* state_in,
                                                   const float* cov_in, const int8_t* __restrict__ charge,
@@ -129,8 +137,18 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
 #pragma unroll
       for (int k = 0; k < KF_RES_FEATURES + 2; ++k) res[k * ldr + i * (L - 1) + (l - 1)] = NAN;
   }
+  // Software pipeline over layers: the hit of layer l + 1 is fetched while
+  // layer l is computed, and the hit index two layers ahead, so the dependent
+  // gathers (index, then hit) overlap the arithmetic instead of stalling it.
+  float m[3] = {0.f, 0.f, 0.f}, v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int32_t h_cur = last >= 0 ? hit_idx[i] : -1;
+  int32_t h_nxt = last >= 1 ? hit_idx[ld_idx + i] : -1;
+  if (h_cur >= 0) load_hit(hit_pos, hit_cov, ldh, h_cur, m, v);
   float r_from = 0.f;
   for (int l = 0; l <= last; ++l) {
+    float mn[3] = {0.f, 0.f, 0.f}, vn[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int32_t h_nn = (l + 2 <= last) ? hit_idx[static_cast<int64_t>(l + 2) * ld_idx + i] : -1;
+    if (h_nxt >= 0) load_hit(hit_pos, hit_cov, ldh, h_nxt, mn, vn);
     T s2[6], c2[21];
 #pragma unroll
     for (int k = 0; k < 6; ++k) s2[k] = s[k];
@@ -138,14 +156,8 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
     for (int k = 0; k < 21; ++k) c2[k] = c[k];
     st = propagate(s2, c2, a, T(g.r[l]), T(0));
     if (st) break;
-    const int32_t h = hit_idx[l * ld_idx + i];
-    if (h >= 0) {
-      float m[3], v[6];
+    if (h_cur >= 0) {
       T dc2;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) m[k] = hit_pos[k * ldh + h];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) v[k] = hit_cov[k * ldh + h];
       if (res && l >= 1) emit_residual(res, ldr, i * (L - 1) + (l - 1), s2, c2, qf, r_from, g.r[l], g.z_half[l], m);
       st = update_on_layer<T, double>(s2, c2, m, v, dc2);
       if (st) break;
@@ -165,6 +177,12 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
 #pragma unroll
       for (int k = 0; k < 21; ++k) c[k] = c2[k];
     }
+    h_cur = h_nxt;
+    h_nxt = h_nn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m[k] = mn[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = vn[k];
   }
   store_track(state_out, cov_out, ld, i, s, c);
   chi2_out[i] = static_cast<float>(chi2);

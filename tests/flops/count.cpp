@@ -1,0 +1,40 @@
+// Counts the floating-point operations of the device Kalman-filter arithmetic
+// by compiling it for the host with a counting number type (every + - * / on
+// it counts one FLOP; square roots, reciprocal square roots, arctangents and
+// logarithms are counted apart).  Built by tests/test_flop_model.py from a
+// host copy of kf_device.hpp; prints one "name value" line per quantity.
+#include <cstdio>
+
+#include "kf_device_cf.hpp"
+
+using namespace kfd;
+static void reset() { cnt_flop = cnt_div = cnt_rsqrt = cnt_atan = cnt_log = cnt_sqrt = 0; }
+static void report(const char* what) {
+  std::printf("%s %lld %lld %lld\n", what, cnt_flop, cnt_div, cnt_rsqrt + cnt_sqrt + cnt_atan + cnt_log);
+  reset();
+}
+int main() {
+  // a track at r = 22 cm crossing to r = 28 cm, a full covariance, a hit near the prediction
+  CF s[6] = {CF(20.0), CF(9.0), CF(3.0), CF(1.2), CF(0.9), CF(0.4)};
+  CF c[21];
+  for (int i = 0; i < 21; ++i) c[i] = CF(1e-6 * (i + 1));
+  for (int i = 0; i < 6; ++i) c[tri(i, i)] = CF(1e-3 * (i + 1));
+  const CF a = CF(-1.0 * kCLight * 3.8);
+  reset();
+  if (propagate(s, c, a, CF(28.0), CF(50.0))) return 1;
+  report("propagate");
+  if (material(s, c, CF(0.02), CF(0.0363), CF(0.13957039))) return 1;
+  report("material");
+  const float m[3] = {static_cast<float>(s[0].v) + 0.004f, static_cast<float>(s[1].v) - 0.003f,
+                      static_cast<float>(s[2].v) + 0.05f};
+  const float v[6] = {1e-4f, 0.f, 1e-4f, 0.f, 0.f, 1e-2f};
+  const LocalPred<CF> lp = local_pred(s, c);
+  report("local_pred");
+  CF c2;
+  if (chi2_on_layer(s, lp, m, v, c2)) return 1;
+  report("chi2");
+  CF dc2;
+  if (update_on_layer<CF, CF>(s, c, m, v, dc2)) return 1;
+  report("update");
+  return 0;
+}
