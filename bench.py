@@ -200,18 +200,24 @@ def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, pl
     torch.cuda.synchronize()
     train_ms = t0.elapsed_time(t1)
     lcfg = KB.make_cfg(max_cands=N, mode=cfg.mode, precision=cfg.precision, window_mode=KB.WINDOW_LEARNED,
-                       learned_nsigma=args.nsigma)
-    lout = KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, mlp_packed=tr.packed)
+                       learned_nsigma=args.nsigma, waves_per_block=cfg.waves_per_block,
+                       blocks_per_cu=cfg.blocks_per_cu)
+    lws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    lout = KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, mlp_packed=tr.packed, workspace=lws)
+    if args.build_mode == "auto":
+        KB.autotune(ctx, lcfg, lout, reps=2)
     cnt = torch.zeros(KB.BUILD_COUNTERS, dtype=torch.int64, device="cuda")
     KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=lout, counters=cnt,
-             mlp_packed=tr.packed)
+             mlp_packed=tr.packed, workspace=lws)
     for _ in range(args.warmup):
-        KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=lout, mlp_packed=tr.packed)
+        KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=lout, mlp_packed=tr.packed,
+                 workspace=lws)
     torch.cuda.synchronize()
     evs = [(E(), E()) for _ in range(args.steps)]
     for a, b in evs:
         a.record(stream)
-        KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=lout, mlp_packed=tr.packed)
+        KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=lout, mlp_packed=tr.packed,
+                 workspace=lws)
         b.record(stream)
     torch.cuda.synchronize()
     lms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
@@ -219,7 +225,9 @@ def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, pl
     e_plain = judge.judge_problem(bp, bout["cand_hits"][:, :S_, 0].T.cpu().numpy())
     e_learn = judge.judge_problem(bp, lout["cand_hits"][:, :S_, 0].T.cpu().numpy())
     c = cnt.cpu().numpy()
-    return {"nsigma": args.nsigma, "build_ms": lms, "plain_build_ms": plain_build_ms,
+    return {"nsigma": args.nsigma, "build_mode": "persistent" if lcfg.mode == KB.BUILD_PERSISTENT else "tiled",
+            "waves_per_block": int(lcfg.waves_per_block), "blocks_per_cu": int(lcfg.blocks_per_cu),
+            "build_ms": lms, "plain_build_ms": plain_build_ms,
             "speedup_vs_plain": plain_build_ms / lms, "seeds_built_per_s_build_only": S_ / (lms * 1e-3),
             "eff_plain": e_plain["eff"], "eff_learned": e_learn["eff"],
             "eff_loss_pp": 100.0 * (e_plain["eff"] - e_learn["eff"]),
@@ -238,8 +246,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tracks", type=int, default=2_000_000)
     ap.add_argument("--events", type=int, default=64)
-    ap.add_argument("--build-mode", choices=["tiled", "persistent"], default="persistent")
-    ap.add_argument("--build-precision", choices=["f32", "f64"], default="f64")
+    ap.add_argument("--build-mode", choices=["auto", "tiled", "persistent"], default="auto",
+                    help="auto: the build autotuner picks mode and launch shape (untimed, before warm-up)")
+    ap.add_argument("--build-precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--fit-fp64", action="store_true", help="double-precision registers in the fit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-window leg")
     ap.add_argument("--nsigma", type=float, default=4.0, help="learned window half width in network scales")
@@ -294,7 +303,13 @@ def main():
     bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events)
     bws_bytes = kfmi.load_library().kf_bin_hits_workspace_size(hits["pos"].shape[1])
     bws = torch.empty(max(bws_bytes, 4), dtype=torch.uint8, device=dev)
-    bout = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events)
+    build_ws = torch.empty(256, dtype=torch.uint8, device=dev)
+    bout = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events, workspace=build_ws)
+    tuned_ms = None
+    if args.build_mode == "auto":
+        tuned_ms = KB.autotune(ctx, cfg, bout, reps=2)
+        print(f"[bench] build autotuned: mode {cfg.mode} waves/block {cfg.waves_per_block} blocks/CU "
+              f"{cfg.blocks_per_cu} ({tuned_ms:.2f} ms)", file=sys.stderr, flush=True)
     cnt = torch.zeros(KB.BUILD_COUNTERS, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
 
@@ -305,7 +320,8 @@ def main():
         KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events, out=bins, workspace=bws)
 
     def build_step(counters=None):
-        KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=bout, counters=counters)
+        KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=bout, counters=counters,
+                 workspace=build_ws)
 
     for _ in range(args.warmup):
         fit_step()
@@ -343,7 +359,7 @@ def main():
     ff = fit_flops(fp)
     kern["fit_kernel"] = dict(avg_ms=fit_ms, flop=ff, bytes=fb)
     kern["bin_kernel"] = dict(avg_ms=bin_ms, flop=0, bytes=bin_bytes(bp, L))
-    kern["build_persistent_kernel" if mode else "build_tiled_kernel"] = dict(
+    kern["build_persistent_kernel" if cfg.mode == KB.BUILD_PERSISTENT else "build_tiled_kernel"] = dict(
         avg_ms=build_ms, flop=build_flops(counters), bytes=build_bytes(bp, N, L))
     for k, v in kern.items():
         sec = v["avg_ms"] * 1e-3
@@ -382,7 +398,10 @@ def main():
                                "then batched build: 64 events log-uniform [1k,50k] tracks + 20% noise hits, "
                                "64x16 bins, N=6, chi2<30",
                    "tracks": n, "layers": L, "fit_hits": n_hits, "events": bp.n_events, "seeds": n_seeds,
-                   "build_hits": int(bp.hit_pos.shape[0]), "build_mode": args.build_mode,
+                   "build_hits": int(bp.hit_pos.shape[0]),
+                   "build_mode": "persistent" if cfg.mode == KB.BUILD_PERSISTENT else "tiled",
+                   "build_waves_per_block": int(cfg.waves_per_block), "build_blocks_per_cu": int(cfg.blocks_per_cu),
+                   "build_autotuned": args.build_mode == "auto",
                    "build_precision": args.build_precision, "fit_fp64": bool(args.fit_fp64)},
         "seeds_built_per_s": seeds_per_s,
         "fit_ms": fit_ms, "bin_ms": bin_ms, "build_ms": build_ms,

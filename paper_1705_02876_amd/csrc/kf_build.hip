@@ -51,8 +51,13 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
                                                           int32_t* __restrict__ bins, int32_t* __restrict__ bin_offsets,
                                                           int32_t* __restrict__ perm, float* __restrict__ binned,
                                                           float* __restrict__ layer_vmax) {
-  __shared__ int32_t cnt[kBinWaves][kMaxBins];
-  __shared__ int32_t tot[kMaxBins];
+  // per-wave bin counters [kBinWaves][nb] and bin totals [nb], sized by the launch (dynamic LDS) so that
+  // a 64 x 16 binning takes 68 KB and two blocks share a compute unit
+  extern __shared__ int32_t bin_lds[];
+  const int nb_ = n_phi * n_eta;
+  int32_t* const cnt_flat = bin_lds;
+  int32_t* const tot = bin_lds + kBinWaves * nb_;
+#define cnt(w, b) cnt_flat[(w) * nb_ + (b)]
   __shared__ int32_t wsum[kBinWaves];
   __shared__ uint32_t vmax_bits[2];
   const int el = blockIdx.x;
@@ -63,7 +68,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
   const int lane = tid & 63;
   const int64_t lo = layer_offsets[el], hi = layer_offsets[el + 1];
   const int64_t nh = hi - lo;
-  for (int i = tid; i < kBinWaves * nb; i += kBinThreads) cnt[i / nb][i % nb] = 0;
+  for (int i = tid; i < kBinWaves * nb; i += kBinThreads) cnt(i / nb, i % nb) = 0;
   if (tid < 2) vmax_bits[tid] = 0u;
   __syncthreads();
   // this wave's contiguous slice
@@ -76,7 +81,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
   for (int64_t h = a + lane; h < b; h += 64) {
     const int bin = hit_bin(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h], R, zh, n_phi, n_eta);
     bins[h] = bin;
-    atomicAdd(&cnt[wave][bin], 1);
+    atomicAdd(&cnt(wave, bin), 1);
     const float vxx = hit_cov[h], vyx = hit_cov[ldh + h], vyy = hit_cov[2 * ldh + h], vzz = hit_cov[5 * ldh + h];
     const float d = 0.5f * (vxx - vyy);
     my_vxy = fmaxf(my_vxy, 0.5f * (vxx + vyy) + sqrtf(d * d + vyx * vyx));
@@ -90,8 +95,8 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
     int run = 0;
 #pragma unroll
     for (int w = 0; w < kBinWaves; ++w) {
-      const int c = cnt[w][bin];
-      cnt[w][bin] = run;
+      const int c = cnt(w, bin);
+      cnt(w, bin) = run;
       run += c;
     }
     tot[bin] = run;
@@ -140,7 +145,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
   for (int bin = tid; bin < nb; bin += kBinThreads) {
     const int base = tot[bin];
 #pragma unroll
-    for (int w = 0; w < kBinWaves; ++w) cnt[w][bin] += base;
+    for (int w = 0; w < kBinWaves; ++w) cnt(w, bin) += base;
   }
   __syncthreads();
   // stable scatter of this wave's slice, 64 hits at a time, in index order
@@ -159,9 +164,9 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int rank = __popcll(m & lt);
     int dest = 0;
-    if (valid) dest = cnt[wave][bin] + rank;
+    if (valid) dest = cnt(wave, bin) + rank;
     __builtin_amdgcn_wave_barrier();
-    if (valid && rank == 0) cnt[wave][bin] += __popcll(m);
+    if (valid && rank == 0) cnt(wave, bin) += __popcll(m);
     __builtin_amdgcn_wave_barrier();
     if (valid) {
       const int64_t slot = lo + dest;
@@ -174,6 +179,8 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
     }
   }
 }
+
+#undef cnt
 
 // ---------------------------------------------------------------------------
 // building
@@ -665,7 +672,13 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
   const int L = ctx->geom.n_layers;
   const int64_t n_el = a->n_events * L;
   if (n_el > INT32_MAX) return set_error(KF_ERR_INVALID_ARG, "too many (event, layer) pairs");
-  bin_kernel<<<static_cast<unsigned>(n_el), kBinThreads, 0, kfh::stream_of(a->stream)>>>(
+  const size_t lds_bytes = static_cast<size_t>(kBinWaves + 1) * a->n_phi * a->n_eta * sizeof(int32_t);
+  if (int32_t rc = kfh::check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(bin_kernel),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      static_cast<int>((kBinWaves + 1) * kMaxBins * sizeof(int32_t))),
+                                  "hipFuncSetAttribute(bin_kernel)"))
+    return rc;
+  bin_kernel<<<static_cast<unsigned>(n_el), kBinThreads, lds_bytes, kfh::stream_of(a->stream)>>>(
       L, a->layer_offsets, a->hit_pos, a->hit_cov, a->ldh, a->n_phi, a->n_eta, ctx->dgeom,
       static_cast<int32_t*>(a->workspace), a->bin_offsets, a->perm, a->binned, a->layer_vmax);
   return kfh::check_hip(hipGetLastError(), "bin_kernel launch");
