@@ -249,6 +249,8 @@ def main():
     ap.add_argument("--build-mode", choices=["auto", "tiled", "persistent"], default="auto",
                     help="auto: the build autotuner picks mode and launch shape (untimed, before warm-up)")
     ap.add_argument("--build-precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--build-wpb", type=int, default=0, help="waves per block when --build-mode is not auto")
+    ap.add_argument("--build-bpc", type=int, default=0, help="persistent blocks per CU when --build-mode is not auto")
     ap.add_argument("--fit-fp64", action="store_true", help="double-precision registers in the fit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-window leg")
     ap.add_argument("--nsigma", type=float, default=4.0, help="learned window half width in network scales")
@@ -299,7 +301,8 @@ def main():
     N = 6
     mode = KB.BUILD_PERSISTENT if args.build_mode == "persistent" else KB.BUILD_TILED
     cfg = KB.make_cfg(max_cands=N, mode=mode,
-                      precision=KB.PREC_F64 if args.build_precision == "f64" else KB.PREC_F32)
+                      precision=KB.PREC_F64 if args.build_precision == "f64" else KB.PREC_F32,
+                      waves_per_block=args.build_wpb, blocks_per_cu=args.build_bpc)
     bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events)
     bws_bytes = kfmi.load_library().kf_bin_hits_workspace_size(hits["pos"].shape[1])
     bws = torch.empty(max(bws_bytes, 4), dtype=torch.uint8, device=dev)

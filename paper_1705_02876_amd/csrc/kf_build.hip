@@ -29,8 +29,8 @@ constexpr int kBinWaves = 16;
 constexpr int kBinThreads = kBinWaves * 64;
 constexpr int kMaxBins = 2048;
 constexpr uint32_t kHole = 0xFFFFFFu;
-constexpr int kScanUnroll = 4;  // hit records box-tested per lane and scan iteration
-constexpr int kPendCap = 16;    // per-lane list of box-passing slots awaiting their chi2
+constexpr int kScanUnroll = 4;                  // work items per lane and scan iteration
+constexpr int kQueueCap = 64 + 64 * kScanUnroll;  // box-passing (candidate, slot) pairs awaiting their chi2
 
 __device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, double zh, int n_phi, int n_eta) {
 #pragma clang fp contract(off)
@@ -253,6 +253,40 @@ __device__ __forceinline__ float wrap_pi(float a) {
   return a;
 }
 
+// Wave-cooperative window scan.  All 64 lanes share the box tests of the wave's
+// candidates: the candidates' slot ranges (one range index r at a time: row
+// ie0 + r/2, segment r%2) are laid end to end and lane i takes items
+// base + 64u + i, so a wide window no longer holds the whole wave to one lane.
+// Box-passing (candidate, slot) pairs are queued in LDS in item order, which is
+// candidate order within a range index; the queue is evaluated 64 pairs at a
+// time (one chi2 per lane) and each candidate then inserts its own compatible
+// hits, which are contiguous in the result list, into its register top-N.
+template <typename T>
+struct ScanLds {
+  float box[7][64];  // px0, py0, pz0, tx, ty, wt, wz of each lane's candidate
+  T pred[8][64];     // x, y, z, nx, ny, att, atz, azz: what a chi2 needs of the candidate
+  int32_t off[64];   // exclusive prefix of the candidates' range lengths
+  int32_t start[64]; // first slot of each candidate's range
+  int32_t q_slot[kQueueCap];
+  int32_t q_own[kQueueCap];
+  int32_t r_own[64], r_idx[64], r_slot[64];
+  T r_c2[64];
+};
+
+// orders this lane's LDS accesses of the wave before and after (the wave executes in lockstep; this keeps the
+// compiler from moving LDS accesses across the point)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
+}
+
 template <int G, typename T, bool LW>
 __device__ void build_tile(const BuildP& p, int64_t tile) {
   constexpr int SPW = 64 / G;  // seeds per wave
@@ -291,11 +325,11 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
   T chi2 = T(0);
   int nhits = 3;
   int nc = seed_ok ? 1 : 0;  // candidates of this seed (same in all its lanes)
-  uint64_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0, n_fb = 0;
+  uint32_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0, n_fb = 0;  // per lane and tile
   const float qf = seed_ok ? static_cast<float>(p.seed_charge[s]) : 1.f;
-  // per-wave pending lists, [slot][lane] so that a wave's accesses hit 64 consecutive words
-  __shared__ int32_t pend_all[4][kPendCap][64];
-  int32_t (*pend)[64] = pend_all[(threadIdx.x >> 6) & 3];
+  __shared__ ScanLds<T> scan_all[4];
+  ScanLds<T>& C = scan_all[(threadIdx.x >> 6) & 3];
+  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const float4* recs = reinterpret_cast<const float4*>(p.binned);
 
   for (int l = p.first_layer; l < L; ++l) {
@@ -349,7 +383,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
     }
     int cnt = 0;
     {
-      // Window geometry of this lane's candidate (dead lanes get an empty scan).
+      // Window geometry of this lane's candidate (dead lanes only work for others).
       const bool live = active && pstat == 0;
       const float R = p.g.r[l];
       const LocalPred<T> lp = local_pred(ps, pc);
@@ -365,6 +399,14 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
       const float emax = asinhf(p.g.z_half[l] / R);
       const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
       const bool tighter = live && (lwt < wt_plain || lwz < wz_plain);
+      C.pred[0][lane] = ps[0];
+      C.pred[1][lane] = ps[1];
+      C.pred[2][lane] = ps[2];
+      C.pred[3][lane] = lp.nx;
+      C.pred[4][lane] = lp.ny;
+      C.pred[5][lane] = lp.att;
+      C.pred[6][lane] = lp.atz;
+      C.pred[7][lane] = lp.azz;
       // pass 0: learned box where it is tighter; pass 1: the plain window for every other live candidate
       // and for those whose learned box held no compatible hit (fallback)
       for (int pass = 0; pass < 2; ++pass) {
@@ -389,85 +431,179 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
         }
         const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
         const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
-        // Slot ranges r = 0 .. rend-1: row ie0 + r/2, segment r%2 (the wrapped part of the phi span).
-        // The loop is wave-synchronous: every iteration box-tests up to 4 slots per lane with their loads
-        // issued together; slots that pass go to this lane's pending list in LDS, and whenever a list
-        // could overflow (and at the end) all lanes evaluate their pending chi2 in lockstep.
-        int r = 0;
-        const int rend = part ? 2 * (ie1 - ie0 + 1) : 0;
-        int j = 0, jend = 0, npend = 0;
-        for (;;) {
-          while (j >= jend && r < rend) {
+        C.box[0][lane] = px0;
+        C.box[1][lane] = py0;
+        C.box[2][lane] = pz0;
+        C.box[3][lane] = tx;
+        C.box[4][lane] = ty;
+        C.box[5][lane] = wt;
+        C.box[6][lane] = wz;
+        const int nr = part ? 2 * (ie1 - ie0 + 1) : 0;
+        const int max_nr = wave_max_i(nr);
+        for (int r = 0; r < max_nr; ++r) {
+          // this lane's r-th slot range
+          int ra = 0, rn = 0;
+          if (r < nr) {
             const int row = (ie0 + (r >> 1)) * p.n_phi;
             if ((r & 1) == 0) {
-              j = bo[row + ip0];
-              jend = bo[row + first_end];
+              ra = bo[row + ip0];
+              rn = bo[row + first_end] - ra;
             } else if (wrap_end > 0) {
-              j = bo[row];
-              jend = bo[row + wrap_end];
-            } else {
-              j = jend = 0;
+              ra = bo[row];
+              rn = bo[row + wrap_end] - ra;
             }
-            ++r;
           }
-          const bool has = j < jend;
-          const bool any = __ballot(has) != 0;
-          if (any && has) {
+          int incl = rn;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+          }
+          const int total = __shfl(incl, 63);
+          if (total == 0) continue;
+          wave_lds_sync();  // the previous range's readers are done with off/start
+          C.off[lane] = incl - rn;
+          C.start[lane] = ra;
+          wave_lds_sync();
+          int qn = 0;
+          for (int base = 0; base < total; base += 64 * kScanUnroll) {
+            int own[kScanUnroll], js[kScanUnroll];
             float4 hv[kScanUnroll];
 #pragma unroll
             for (int u = 0; u < kScanUnroll; ++u) {
-              const int jc = (j + u < jend) ? j + u : jend - 1;
-              hv[u] = recs[static_cast<int64_t>(jc) * 3];
+              const int w = base + 64 * u + lane;
+              const int wc = w < total ? w : total - 1;
+              int lo = 0;  // largest candidate lane whose range starts at or before item wc
+#pragma unroll
+              for (int step = 32; step > 0; step >>= 1)
+                if (C.off[lo + step] <= wc) lo += step;
+              own[u] = lo;
+              js[u] = C.start[lo] + (wc - C.off[lo]);
+              hv[u] = recs[static_cast<int64_t>(js[u]) * 3];
             }
 #pragma unroll
             for (int u = 0; u < kScanUnroll; ++u) {
-              if (j + u < jend) {
+              const int w = base + 64 * u + lane;
+              bool pass_box = false;
+              if (w < total) {
                 n_box++;
-                const float dx = hv[u].x - px0, dy = hv[u].y - py0, dz = hv[u].z - pz0;
-                if (fabsf(tx * dx + ty * dy) <= wt && fabsf(dz) <= wz) pend[npend++][lane] = j + u;
+                const int o = own[u];
+                const float dx = hv[u].x - C.box[0][o], dy = hv[u].y - C.box[1][o], dz = hv[u].z - C.box[2][o];
+                pass_box = fabsf(C.box[3][o] * dx + C.box[4][o] * dy) <= C.box[5][o] && fabsf(dz) <= C.box[6][o];
               }
+              const uint64_t m = __ballot(pass_box);
+              if (pass_box) {
+                const int pos = qn + __popcll(m & lanes_below);
+                C.q_slot[pos] = js[u];
+                C.q_own[pos] = own[u];
+              }
+              qn += __popcll(m);
             }
-            j = (j + kScanUnroll < jend) ? j + kScanUnroll : jend;
-          }
-          const bool last_round = !any;
-          if (last_round || __ballot(npend > kPendCap - kScanUnroll) != 0) {
-            int m = npend;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
-            for (int k = 0; k < m; ++k) {
-              if (k < npend) {
-                const int js = pend[k][lane];
-                const float4 h = recs[static_cast<int64_t>(js) * 3];
-                const float4 c0 = recs[static_cast<int64_t>(js) * 3 + 1];
-                const float4 c1 = recs[static_cast<int64_t>(js) * 3 + 2];
+            // evaluate full batches of 64 (and, after the last items of this range, the rest)
+            const bool range_done = base + 64 * kScanUnroll >= total;
+            while (qn >= 64 || (range_done && qn > 0)) {
+              wave_lds_sync();
+              const int nb = qn < 64 ? qn : 64;
+              bool comp = false;
+              T c2 = T(0);
+              int32_t hidx = 0, jq = 0, oq = 0;
+              if (lane < nb) {
+                jq = C.q_slot[lane];
+                oq = C.q_own[lane];
+                const float4 h = recs[static_cast<int64_t>(jq) * 3];
+                const float4 c0 = recs[static_cast<int64_t>(jq) * 3 + 1];
+                const float4 c1 = recs[static_cast<int64_t>(jq) * 3 + 2];
                 const float mm[3] = {h.x, h.y, h.z};
                 const float vv[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
-                T c2;
+                T pos3[6];
+                pos3[0] = C.pred[0][oq];
+                pos3[1] = C.pred[1][oq];
+                pos3[2] = C.pred[2][oq];
+                LocalPred<T> L;
+                L.nx = C.pred[3][oq];
+                L.ny = C.pred[4][oq];
+                L.tx = -L.ny;
+                L.ty = L.nx;
+                L.att = C.pred[5][oq];
+                L.atz = C.pred[6][oq];
+                L.azz = C.pred[7][oq];
                 n_chi2++;
-                if (!chi2_on_layer(ps, lp, mm, vv, c2) && c2 < T(p.chi2_cut)) {
+                if (!chi2_on_layer(pos3, L, mm, vv, c2) && c2 < T(p.chi2_cut)) {
+                  comp = true;
                   n_comp++;
-                  T nk = chi2 + (c2 > T(0) ? c2 : T(0));
-                  int32_t ni = __float_as_int(h.w);
-                  int32_t nj = js;
+                  hidx = __float_as_int(h.w);
+                }
+              }
+              const uint64_t rm = __ballot(comp);
+              const int nres = __popcll(rm);
+              wave_lds_sync();  // queue entries read; results may be written
+              if (comp) {
+                const int rp = __popcll(rm & lanes_below);
+                C.r_own[rp] = oq;
+                C.r_idx[rp] = hidx;
+                C.r_slot[rp] = jq;
+                C.r_c2[rp] = c2;
+              }
+              // move the unevaluated rest of the queue to its front
+              const int rest = qn - nb;
+              int keep_s[kScanUnroll + 1], keep_o[kScanUnroll + 1];
 #pragma unroll
-                  for (int t = 0; t < G; ++t) {
-                    const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
-                    const T tk = lkey[t];
-                    const int32_t ti = lidx[t], tj = lslot[t];
-                    lkey[t] = sw ? nk : tk;
-                    lidx[t] = sw ? ni : ti;
-                    lslot[t] = sw ? nj : tj;
-                    nk = sw ? tk : nk;
-                    ni = sw ? ti : ni;
-                    nj = sw ? tj : nj;
+              for (int u = 0; u <= kScanUnroll; ++u) {
+                const int from = nb + 64 * u + lane;
+                keep_s[u] = from < qn ? C.q_slot[from] : 0;
+                keep_o[u] = from < qn ? C.q_own[from] : 0;
+              }
+              wave_lds_sync();
+#pragma unroll
+              for (int u = 0; u <= kScanUnroll; ++u) {
+                const int to = 64 * u + lane;
+                if (to < rest) {
+                  C.q_slot[to] = keep_s[u];
+                  C.q_own[to] = keep_o[u];
+                }
+              }
+              qn = rest;
+              wave_lds_sync();
+              if (nres > 0) {
+                // this lane's results are contiguous (the batch is in candidate order)
+                int lo = 0, hi = nres;
+                while (lo < hi) {
+                  const int mid = (lo + hi) >> 1;
+                  if (C.r_own[mid] < lane) lo = mid + 1; else hi = mid;
+                }
+                const int first = lo;
+                hi = nres;
+                while (lo < hi) {
+                  const int mid = (lo + hi) >> 1;
+                  if (C.r_own[mid] <= lane) lo = mid + 1; else hi = mid;
+                }
+                const int count = lo - first;
+                const int rounds = wave_max_i(count);
+                for (int k = 0; k < rounds; ++k) {
+                  if (k < count) {
+                    const int e = first + k;
+                    const T cc = C.r_c2[e];
+                    T nk = chi2 + (cc > T(0) ? cc : T(0));
+                    int32_t ni = C.r_idx[e];
+                    int32_t nj = C.r_slot[e];
+#pragma unroll
+                    for (int t = 0; t < G; ++t) {
+                      const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
+                      const T tk = lkey[t];
+                      const int32_t ti = lidx[t], tj = lslot[t];
+                      lkey[t] = sw ? nk : tk;
+                      lidx[t] = sw ? ni : ti;
+                      lslot[t] = sw ? nj : tj;
+                      nk = sw ? tk : nk;
+                      ni = sw ? ti : ni;
+                      nj = sw ? tj : nj;
+                    }
+                    cnt = cnt + 1 < N ? cnt + 1 : N;
                   }
-                  cnt = cnt + 1 < N ? cnt + 1 : N;
                 }
               }
             }
-            npend = 0;
           }
-          if (last_round) break;
         }
       }
     }
