@@ -202,7 +202,7 @@ def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, pl
     lcfg = KB.make_cfg(max_cands=N, mode=cfg.mode, precision=cfg.precision, window_mode=KB.WINDOW_LEARNED,
                        learned_nsigma=args.nsigma, waves_per_block=cfg.waves_per_block,
                        blocks_per_cu=cfg.blocks_per_cu)
-    lws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    lws = torch.empty(KB.workspace_bytes(lcfg, bp.n_events, seeds["n"]), dtype=torch.uint8, device="cuda")
     lout = KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, mlp_packed=tr.packed, workspace=lws)
     if args.build_mode == "auto":
         KB.autotune(ctx, lcfg, lout, reps=2)
@@ -306,7 +306,7 @@ def main():
     bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events)
     bws_bytes = kfmi.load_library().kf_bin_hits_workspace_size(hits["pos"].shape[1])
     bws = torch.empty(max(bws_bytes, 4), dtype=torch.uint8, device=dev)
-    build_ws = torch.empty(256, dtype=torch.uint8, device=dev)
+    build_ws = torch.empty(KB.workspace_bytes(cfg, bp.n_events, seeds["n"]), dtype=torch.uint8, device=dev)
     bout = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events, workspace=build_ws)
     tuned_ms = None
     if args.build_mode == "auto":

@@ -256,6 +256,8 @@ typedef struct {
   int32_t blocks_per_cu;   /* persistent mode occupancy, 0 = library choice */
   int32_t precision;       /* KF_PREC_F32 or KF_PREC_F64: candidate registers (HBM is float32 either way) */
   float learned_nsigma;    /* KF_WINDOW_LEARNED: half widths in units of the network's scales, > 0 */
+  int32_t seed_order;      /* 1: process each event's seeds grouped by direction (needs workspace); 0: as given.
+                              Results do not depend on it. */
 } kf_build_cfg;
 typedef struct {
   int64_t n_events, n_seeds, ld_seed;
@@ -282,7 +284,11 @@ typedef struct {
   void* stream;
   const void* mlp_packed; /* KF_WINDOW_LEARNED: KF_MLP_PACKED_BYTES from kf_mlp_pack, else ignored */
 } kf_build_args;
-size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_seeds);
+/* Device workspace of kf_build for this configuration and problem size (0 if
+ * none is needed): the persistent work queue and, with seed_order, the
+ * direction cells of every event and the seed order.  Contents on entry are
+ * irrelevant; kf_build overwrites what it uses. */
+size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_events, int64_t n_seeds);
 int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* args);
 
 
@@ -343,7 +349,7 @@ void kf_graph_destroy(kf_graph* graph);
 /* kf_build_autotune: synchronous.  Times kf_build (cfg as given, args as
  * given, counters ignored) over the launch shapes {tiled, persistent} x
  * waves_per_block {1, 2, 4} x blocks_per_cu {1, 2, 4, 8} (persistent only if
- * args carries a workspace), `reps` timed runs each after one warm-up, and
+ * args carries a large enough workspace), `reps` timed runs each after one warm-up, and
  * writes the fastest mode / waves_per_block / blocks_per_cu into *cfg and its
  * average time into *best_ms (nullable).  The outputs in args are
  * overwritten like by any build.  Results are cached in the context per

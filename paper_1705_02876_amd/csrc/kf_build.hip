@@ -208,6 +208,7 @@ struct BuildP {
   float* best_cov;
   unsigned long long* counters;
   int32_t* queue;
+  const int32_t* order;      // tile position -> seed index (seeds grouped by direction), or null
   const unsigned char* mlp;  // packed search-window network, or null for the plain window
   float nsigma;
   Geom g;
@@ -293,8 +294,9 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
   const int lane = threadIdx.x & 63;
   const int slot = lane % G;
   const int gbase = lane - slot;
-  const int64_t s = tile * SPW + lane / G;
-  const bool seed_ok = s < p.n_seeds;
+  const int64_t pos = tile * SPW + lane / G;
+  const bool seed_ok = pos < p.n_seeds;
+  const int64_t s = (seed_ok && p.order) ? static_cast<int64_t>(p.order[pos]) : pos;
   const int L = p.g.n_layers;
   const int N = p.max_cands;
   // event of this seed
@@ -743,6 +745,87 @@ __global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t
   }
 }
 
+// ---------------------------------------------------------------------------
+// seed ordering: seeds of an event grouped by the direction of their position
+// (kSeedPhi x kSeedEta cells), so that a wave's windows fall on neighbouring
+// bins and share cached hit records.  Results do not depend on the order.
+// ---------------------------------------------------------------------------
+constexpr int kSeedPhi = 64, kSeedEta = 32, kSeedCells = kSeedPhi * kSeedEta;
+
+__device__ __forceinline__ int seed_event_of(const int64_t* seed_offsets, int n_events, int64_t s) {
+  int lo = 0, hi = n_events;  // seed_offsets[lo] <= s < seed_offsets[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (seed_offsets[mid] <= s) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int seed_cell(const float* __restrict__ st, int64_t ld, int64_t s) {
+  const float x = st[s], y = st[ld + s], z = st[2 * ld + s];
+  const float r = sqrtf(x * x + y * y);
+  const float phi = atan2f(y, x);
+  const float eta = asinhf(z / r);
+  if (!(r > 0.f) || !isfinite(phi) || !isfinite(eta)) return 0;
+  int ip = static_cast<int>((phi + 3.14159265f) * (kSeedPhi / 6.2831853f));
+  int ie = static_cast<int>((eta + 2.f) * (kSeedEta / 4.f));
+  ip = ip < 0 ? 0 : (ip > kSeedPhi - 1 ? kSeedPhi - 1 : ip);
+  ie = ie < 0 ? 0 : (ie > kSeedEta - 1 ? kSeedEta - 1 : ie);
+  return ip * kSeedEta + ie;
+}
+
+__global__ void __launch_bounds__(256) seed_count_kernel(int64_t n_seeds, int32_t n_events,
+                                                         const int64_t* __restrict__ seed_offsets,
+                                                         const float* __restrict__ st, int64_t ld,
+                                                         int32_t* __restrict__ cells) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n_seeds) return;
+  const int e = seed_event_of(seed_offsets, n_events, s);
+  atomicAdd(&cells[static_cast<int64_t>(e) * kSeedCells + seed_cell(st, ld, s)], 1);
+}
+
+// one block per event: exclusive scan of its cell counts, offset by the event's first seed
+__global__ void __launch_bounds__(1024) seed_scan_kernel(const int64_t* __restrict__ seed_offsets,
+                                                         int32_t* __restrict__ cells) {
+  __shared__ int32_t part[1024];
+  const int e = blockIdx.x;
+  int32_t* c = cells + static_cast<int64_t>(e) * kSeedCells;
+  constexpr int per = kSeedCells / 1024;
+  const int t = threadIdx.x;
+  int32_t v[per];
+  int32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    v[k] = c[t * per + k];
+    sum += v[k];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int32_t y = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += y;
+    __syncthreads();
+  }
+  int32_t run = static_cast<int32_t>(seed_offsets[e]) + part[t] - sum;
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    c[t * per + k] = run;
+    run += v[k];
+  }
+}
+
+__global__ void __launch_bounds__(256) seed_scatter_kernel(int64_t n_seeds, int32_t n_events,
+                                                           const int64_t* __restrict__ seed_offsets,
+                                                           const float* __restrict__ st, int64_t ld,
+                                                           int32_t* __restrict__ cells, int32_t* __restrict__ order) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n_seeds) return;
+  const int e = seed_event_of(seed_offsets, n_events, s);
+  const int32_t at = atomicAdd(&cells[static_cast<int64_t>(e) * kSeedCells + seed_cell(st, ld, s)], 1);
+  order[at] = static_cast<int32_t>(s);
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -820,10 +903,17 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
   return kfh::check_hip(hipGetLastError(), "bin_kernel launch");
 }
 
-size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_seeds) {
-  (void)n_seeds;
-  if (cfg && cfg->mode == KF_BUILD_PERSISTENT) return 256;
-  return 0;
+namespace {
+constexpr size_t kQueueBytes = 256;
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+size_t cells_bytes(int64_t n_events) { return align256(static_cast<size_t>(n_events) * kSeedCells * 4); }
+}  // namespace
+
+size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_events, int64_t n_seeds) {
+  if (!cfg || n_events < 0 || n_seeds < 0) return 0;
+  size_t b = kQueueBytes;  // persistent work queue (kept in every layout)
+  if (cfg->seed_order) b += cells_bytes(n_events) + align256(static_cast<size_t>(n_seeds) * 4);
+  return (cfg->mode == KF_BUILD_PERSISTENT || cfg->seed_order) ? b : 0;
 }
 
 int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
@@ -897,6 +987,26 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   const int wpb = cfg->waves_per_block > 0 ? cfg->waves_per_block : 4;
   if (wpb > 4) return set_error(KF_ERR_INVALID_ARG, "waves_per_block must be 1..4");
   hipStream_t stream = kfh::stream_of(a->stream);
+  const size_t need = kf_build_workspace_size(cfg, a->n_events, a->n_seeds);
+  if (need > 0 && (!a->workspace || a->workspace_bytes < need))
+    return set_error(KF_ERR_WORKSPACE, "this configuration needs kf_build_workspace_size() = %zu bytes of workspace",
+                     need);
+  p.order = nullptr;
+  if (cfg->seed_order) {
+    if (a->n_seeds > INT32_MAX) return set_error(KF_ERR_INVALID_ARG, "seed_order needs n_seeds < 2^31");
+    unsigned char* w = static_cast<unsigned char*>(a->workspace);
+    int32_t* cells = reinterpret_cast<int32_t*>(w + kQueueBytes);
+    int32_t* order = reinterpret_cast<int32_t*>(w + kQueueBytes + cells_bytes(a->n_events));
+    const int64_t nc = a->n_events * kSeedCells;
+    fill_i32_kernel<<<kfh::grid_for(nc, 256), 256, 0, stream>>>(cells, nc, 0);
+    seed_count_kernel<<<kfh::grid_for(a->n_seeds, 256), 256, 0, stream>>>(
+        a->n_seeds, static_cast<int32_t>(a->n_events), a->seed_offsets, a->seed_state, a->ld_seed, cells);
+    seed_scan_kernel<<<static_cast<unsigned>(a->n_events), 1024, 0, stream>>>(a->seed_offsets, cells);
+    seed_scatter_kernel<<<kfh::grid_for(a->n_seeds, 256), 256, 0, stream>>>(
+        a->n_seeds, static_cast<int32_t>(a->n_events), a->seed_offsets, a->seed_state, a->ld_seed, cells, order);
+    if (int32_t rc = kfh::check_hip(hipGetLastError(), "seed ordering launch")) return rc;
+    p.order = order;
+  }
   const bool f64 = cfg->precision == KF_PREC_F64;
   Launch lc;
   lc.f64 = f64;
@@ -910,8 +1020,6 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
     launch_any(G, lc, p);
     return kfh::check_hip(hipGetLastError(), "build_tiled_kernel launch");
   }
-  if (!a->workspace || a->workspace_bytes < kf_build_workspace_size(cfg, a->n_seeds))
-    return set_error(KF_ERR_WORKSPACE, "persistent mode needs kf_build_workspace_size() bytes of workspace");
   p.queue = static_cast<int32_t*>(a->workspace);
   fill_i32_kernel<<<1, 64, 0, stream>>>(p.queue, 1, 0);
   const int bpc = cfg->blocks_per_cu > 0 ? cfg->blocks_per_cu : 2;

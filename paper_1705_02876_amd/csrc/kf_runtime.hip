@@ -96,7 +96,9 @@ int32_t kf_build_autotune(kf_ctx* ctx, kf_build_cfg* cfg, const kf_build_args* a
   }
   kf_tuned best;
   best.ms = INFINITY;
-  const bool can_persist = a.workspace && a.workspace_bytes >= 256;
+  kf_build_cfg pc = *cfg;
+  pc.mode = KF_BUILD_PERSISTENT;
+  const bool can_persist = a.workspace && a.workspace_bytes >= kf_build_workspace_size(&pc, a.n_events, a.n_seeds);
   const int wpbs[3] = {1, 2, 4};
   const int bpcs[4] = {1, 2, 4, 8};
   int32_t rc = KF_OK;

@@ -24,7 +24,7 @@ class kf_build_cfg(C.Structure):
         ("max_cands", C.c_int32), ("chi2_cut", C.c_float), ("n_phi", C.c_int32), ("n_eta", C.c_int32),
         ("window_margin", C.c_float), ("mode", C.c_int32), ("window_mode", C.c_int32),
         ("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("precision", C.c_int32),
-        ("learned_nsigma", C.c_float),
+        ("learned_nsigma", C.c_float), ("seed_order", C.c_int32),
     ]
 
 
@@ -48,7 +48,7 @@ def declare(lib):
     lib.kf_bin_hits.restype = I32
     lib.kf_bin_hits.argtypes = [P, P]
     lib.kf_build_workspace_size.restype = C.c_size_t
-    lib.kf_build_workspace_size.argtypes = [P, I64]
+    lib.kf_build_workspace_size.argtypes = [P, I64, I64]
     lib.kf_build.restype = I32
     lib.kf_build.argtypes = [P, P, P]
     lib.kf_graph_begin.restype = I32
@@ -115,9 +115,23 @@ def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16,
 
 
 def make_cfg(max_cands=6, chi2_cut=30.0, n_phi=64, n_eta=16, window_margin=0.01, mode=BUILD_TILED,
-             window_mode=WINDOW_PLAIN, waves_per_block=0, blocks_per_cu=0, precision=PREC_F64, learned_nsigma=4.0):
+             window_mode=WINDOW_PLAIN, waves_per_block=0, blocks_per_cu=0, precision=PREC_F64, learned_nsigma=4.0,
+             seed_order=1):
     return kf_build_cfg(max_cands, chi2_cut, n_phi, n_eta, window_margin, mode, window_mode, waves_per_block,
-                        blocks_per_cu, precision, learned_nsigma)
+                        blocks_per_cu, precision, learned_nsigma, seed_order)
+
+
+def workspace_bytes(cfg, n_events, n_seeds):
+    """kf_build_workspace_size for a configuration; the largest over the launch modes when the autotuner may
+    switch modes."""
+    from . import kfmi
+    lib = kfmi.load_library()
+    best = 0
+    for mode in (BUILD_TILED, BUILD_PERSISTENT):
+        c = kf_build_cfg.from_buffer_copy(cfg)
+        c.mode = mode
+        best = max(best, int(lib.kf_build_workspace_size(C.byref(c), int(n_events), int(n_seeds))))
+    return best
 
 
 def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=None, counters=None, workspace=None,
@@ -147,9 +161,11 @@ def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=Non
                    cand_status=torch.empty(max(S, 1), N, dtype=torch.int32, device=dev),
                    best_state=torch.empty(6, ld, dtype=torch.float32, device=dev),
                    best_cov=torch.empty(21, ld, dtype=torch.float32, device=dev))
-    wsb = lib.kf_build_workspace_size(C.byref(cfg), S)
+    wsb = workspace_bytes(cfg, n_events, S)
     if workspace is None and wsb > 0:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    if workspace is not None and workspace.numel() < wsb:
+        raise ValueError(f"workspace of {workspace.numel()} bytes, {wsb} needed (kfmi_build.workspace_bytes)")
     a = kf_build_args()
     a.n_events, a.n_seeds, a.ld_seed, a.first_layer = n_events, S, ld, first_layer
     a.seed_offsets, a.seed_state, a.seed_cov = _ptr(seeds["offsets"]), _ptr(seeds["state"]), _ptr(seeds["cov"])

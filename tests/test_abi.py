@@ -44,3 +44,29 @@ def test_last_error_is_a_string_without_gpu():
     rc = lib.kf_ctx_create(ctypes.byref(h), 0)
     assert rc != 0 and not h.value
     assert isinstance(lib.kf_last_error(), bytes)
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """The ctypes structures have the sizes and field offsets the C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    from paper_1705_02876_amd import kfmi_build as KB
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"kf_geometry": kfmi.kf_geometry, "kf_fit_args": kfmi.kf_fit_args, "kf_bin_args": KB.kf_bin_args,
+               "kf_build_cfg": KB.kf_build_cfg, "kf_build_args": KB.kf_build_args}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{kfmi.HEADER}"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, f"{name}.{fname}"

@@ -46,7 +46,7 @@ def test_graph_replays_bin_and_build(ctx, mode):
     ldh = hits["pos"].shape[1]
     bws = torch.empty(max(kfmi.load_library().kf_bin_hits_workspace_size(ldh), 4), dtype=torch.uint8, device="cuda")
     cfg = KB.make_cfg(mode=mode)
-    wsb = torch.empty(256, dtype=torch.uint8, device="cuda")
+    wsb = torch.empty(KB.workspace_bytes(cfg, prob.n_events, seeds["n"]), dtype=torch.uint8, device="cuda")
     bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events, workspace=bws)
     eager = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, workspace=wsb)
     torch.cuda.synchronize()
@@ -93,7 +93,7 @@ def test_autotune_picks_valid_shape_and_caches(ctx, tmp_path):
     seeds, hits = KB.upload_problem(prob)
     bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events)
     cfg = KB.make_cfg(precision=KB.PREC_F32)
-    wsb = torch.empty(256, dtype=torch.uint8, device="cuda")
+    wsb = torch.empty(KB.workspace_bytes(cfg, prob.n_events, seeds["n"]), dtype=torch.uint8, device="cuda")
     ref = _host(KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, workspace=wsb))
     out = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, workspace=wsb)
     ms = KB.autotune(ctx, cfg, out, reps=2)
