@@ -290,49 +290,62 @@ int32_t or_material_one(const or_geometry* g, int32_t layer, double* s, double* 
 }
 
 /* 3x3 inverse by cofactors; returns 0 if the matrix is not positive definite. */
-static int inv3_pd(const double* R, double* Ri) {
-  double a = R[0], b = R[1], c = R[2], d = R[3], e = R[4], f = R[5], gg = R[6], h = R[7], i = R[8];
-  double m2 = a * e - b * d;
-  double det = a * (e * i - f * h) - b * (d * i - f * gg) + c * (d * h - e * gg);
-  if (!(a > 0.0) || !(m2 > 0.0) || !(det > 0.0)) return 0;
-  Ri[0] = (e * i - f * h) / det;
-  Ri[1] = (c * h - b * i) / det;
-  Ri[2] = (b * f - c * e) / det;
-  Ri[3] = (f * gg - d * i) / det;
-  Ri[4] = (a * i - c * gg) / det;
-  Ri[5] = (c * d - a * f) / det;
-  Ri[6] = (d * h - e * gg) / det;
-  Ri[7] = (b * gg - a * h) / det;
-  Ri[8] = (a * e - b * d) / det;
+/* Cholesky factor R = L L^T of a symmetric 3x3 matrix (lower triangle read);
+ * 0 unless R is positive definite.  A backward-stable factorisation: the
+ * residual covariance of a crossing near the tangent point has a condition
+ * number near 1e7, where an explicit cofactor inverse loses the gain. */
+static int chol3(const double* R, double* L) {
+  double d0 = R[0];
+  if (!(d0 > 0.0)) return 0;
+  double l00 = sqrt(d0);
+  double l10 = R[3] / l00, l20 = R[6] / l00;
+  double d1 = R[4] - l10 * l10;
+  if (!(d1 > 0.0)) return 0;
+  double l11 = sqrt(d1);
+  double l21 = (R[7] - l20 * l10) / l11;
+  double d2 = R[8] - l20 * l20 - l21 * l21;
+  if (!(d2 > 0.0)) return 0;
+  L[0] = l00; L[1] = 0.0; L[2] = 0.0;
+  L[3] = l10; L[4] = l11; L[5] = 0.0;
+  L[6] = l20; L[7] = l21; L[8] = sqrt(d2);
   return 1;
 }
 
+/* x = (L L^T)^-1 b */
+static void chol3_solve(const double* L, const double* b, double* x) {
+  double y0 = b[0] / L[0];
+  double y1 = (b[1] - L[3] * y0) / L[4];
+  double y2 = (b[2] - L[6] * y0 - L[7] * y1) / L[8];
+  x[2] = y2 / L[8];
+  x[1] = (y1 - L[7] * x[2]) / L[4];
+  x[0] = (y0 - L[3] * x[1] - L[6] * x[2]) / L[0];
+}
+
 /* Measurement model H = [I3 0]: residual r = m - H x, R = H C H^T + V,
- * chi2 = r^T R^-1 r, gain K = C H^T R^-1, x += K r, C -= K H C. */
+ * chi2 = r^T R^-1 r, gain K = C H^T R^-1, x += K r, C -= K H C; R^-1 applied
+ * through its Cholesky factor. */
 int32_t or_update_one(double* s, double* C, const double* m, const double* V, double* chi2, int32_t chi2_only) {
-  double R[9], Ri[9];
+  double R[9], L[9];
   if (!finite_n(s, 6) || !finite_n(C, 36)) return OR_NONFINITE;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) R[i * 3 + j] = C[i * 6 + j] + V[i * 3 + j];
-  if (!inv3_pd(R, Ri)) return OR_NOT_PD;
+  if (!chol3(R, L)) return OR_NOT_PD;
   double r[3] = {m[0] - s[0], m[1] - s[1], m[2] - s[2]};
-  double c2 = 0.0;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) c2 += r[i] * Ri[i * 3 + j] * r[j];
-  *chi2 = c2;
+  double Rir[3];
+  chol3_solve(L, r, Rir);
+  *chi2 = r[0] * Rir[0] + r[1] * Rir[1] + r[2] * Rir[2];
   if (chi2_only) return 0;
-  double CHt[18], K[18], HC[18], KHC[36];
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 3; ++j) CHt[i * 3 + j] = C[i * 6 + j];
-  mat_mul(6, 3, 3, CHt, Ri, K);
+  /* K^T = R^-1 H C: column i of H C is (C[0][i], C[1][i], C[2][i]) */
+  double K[18], HC[18], KHC[36];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 6; ++j) HC[i * 6 + j] = C[i * 6 + j];
-  mat_mul(6, 3, 6, K, HC, KHC);
   for (int i = 0; i < 6; ++i) {
-    double d = 0.0;
-    for (int j = 0; j < 3; ++j) d += K[i * 3 + j] * r[j];
-    s[i] += d;
+    double col[3] = {C[0 * 6 + i], C[1 * 6 + i], C[2 * 6 + i]}, x[3];
+    chol3_solve(L, col, x);
+    for (int j = 0; j < 3; ++j) K[i * 3 + j] = x[j];
   }
+  mat_mul(6, 3, 6, K, HC, KHC);
+  for (int i = 0; i < 6; ++i) s[i] += K[i * 3 + 0] * r[0] + K[i * 3 + 1] * r[1] + K[i * 3 + 2] * r[2];
   for (int k = 0; k < 36; ++k) C[k] -= KHC[k];
   symmetrize6(C);
   if (!finite_n(s, 6) || !finite_n(C, 36)) return OR_NONFINITE;

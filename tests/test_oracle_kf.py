@@ -212,3 +212,48 @@ def test_batched_forms_match_single(orc):
         code, s1, C1 = orc.propagate_one(g, fp.state0[i], fp.cov0[i], fp.q[i], det.radii[0])
         assert code == status[i]
         assert np.array_equal(s1, st[i]) and np.array_equal(C1, cov[i])
+
+
+def test_update_is_accurate_for_an_ill_conditioned_residual_covariance(orc):
+    """A crossing near the tangent point: the predicted position has a tangential variance ~2e3 cm^2 and no
+    radial variance, so R = H C H^T + V has condition ~1e7.  The oracle's update must agree with a 50-digit
+    evaluation of the same formulas (a cofactor inverse of R is off by an order of magnitude here)."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    rng = np.random.Generator(np.random.PCG64(17))
+    phi = 0.7
+    n = np.array([np.cos(phi), np.sin(phi), 0.0])
+    t = np.array([-np.sin(phi), np.cos(phi), 0.0])
+    z = np.array([0.0, 0.0, 1.0])
+    # position block: variances 2e3 (t), 0.05 (z), 0 (n), correlated with a generic momentum block
+    A = rng.normal(size=(6, 6)) * 1e-3
+    Mom = A @ A.T + np.eye(6) * 1e-6
+    Cm = np.zeros((6, 6))
+    B = np.stack([t * np.sqrt(2e3), z * np.sqrt(0.05)], axis=1)  # (3, 2)
+    G = rng.normal(size=(2, 3)) * 1e-2                            # position-momentum coupling
+    Cm[:3, :3] = B @ B.T
+    Cm[:3, 3:] = B @ G
+    Cm[3:, :3] = (B @ G).T
+    Cm[3:, 3:] = G.T @ G + Mom[:3, :3]
+    s = np.array([30.0 * n[0], 30.0 * n[1], 5.0, 0.2, 1.3, 0.4])
+    m = s[:3] + 0.01 * t + 0.02 * z + 0.003 * n
+    V = np.diag([1e-4, 1e-4, 1e-2])
+    st, so, co, c2 = orc.update_one(s, Cm, m, V)
+    assert st == 0
+    Cx = mp.matrix(Cm.tolist())
+    H = mp.zeros(3, 6)
+    for i in range(3):
+        H[i, i] = 1
+    Rm = H * Cx * H.T + mp.matrix(V.tolist())
+    Ri = mp.inverse(Rm)
+    K = Cx * H.T * Ri
+    rr = mp.matrix((m - s[:3]).tolist())
+    s_ex = np.array([float(v) for v in (mp.matrix(s.tolist()) + K * rr)])
+    C_ex = np.array([[float(v) for v in row] for row in (Cx - K * H * Cx).tolist()])
+    chi2_ex = float((rr.T * Ri * rr)[0])
+    d = np.sqrt(np.maximum(np.diag(C_ex), 0.0))
+    d[0] = d[1] = np.sqrt(C_ex[0, 0] + C_ex[1, 1])
+    assert np.abs(co - C_ex).max() / 1.0 < 1e-6 * np.outer(d, d).max()
+    assert np.all(np.abs(co - C_ex) <= 1e-6 * np.outer(d, d) + 1e-18)
+    assert np.abs(so - s_ex).max() < 1e-10
+    assert abs(c2 - chi2_ex) < 1e-8 * max(chi2_ex, 1.0)
