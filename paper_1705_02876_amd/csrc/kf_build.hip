@@ -289,7 +289,7 @@ __device__ __forceinline__ int wave_max_i(int v) {
 }
 
 template <int G, typename T, bool LW>
-__device__ void build_tile(const BuildP& p, int64_t tile) {
+__device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* mlp_lds) {
   constexpr int SPW = 64 / G;  // seeds per wave
   const int lane = threadIdx.x & 63;
   const int slot = lane % G;
@@ -368,7 +368,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
         for (int k = 0; k < 8; ++k) f[k] = 0.f;
       }
       float o0, o1;
-      kfm::eval_wave(p.mlp, f, lane, o0, o1);
+      kfm::eval_wave_lds(mlp_lds, f, lane, o0, o1);
       if (use) {
         lwt = p.nsigma * __expf(o0);
         lwz = p.nsigma * __expf(o1);
@@ -727,21 +727,37 @@ __device__ void build_tile(const BuildP& p, int64_t tile) {
   }
 }
 
+// forward weights of the window network, staged once per block (learned-window kernels only)
+template <bool LW>
+struct MlpLds {
+  __device__ static const unsigned char* stage(const unsigned char*) { return nullptr; }
+};
+template <>
+struct MlpLds<true> {
+  __device__ static const unsigned char* stage(const unsigned char* packed) {
+    __shared__ __align__(16) unsigned char w[kfm::kFwdBytes];
+    kfm::stage_forward(packed, w);
+    return w;
+  }
+};
+
 template <int G, typename T, bool LW>
 __global__ void __launch_bounds__(256) build_tiled_kernel(BuildP p) {
+  const unsigned char* wl = MlpLds<LW>::stage(p.mlp);
   const int64_t tile = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  build_tile<G, T, LW>(p, tile);
+  build_tile<G, T, LW>(p, tile, wl);
 }
 
 template <int G, typename T, bool LW>
 __global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t n_tiles) {
+  const unsigned char* wl = MlpLds<LW>::stage(p.mlp);
   const int lane = threadIdx.x & 63;
   for (;;) {
     int32_t t = 0;
     if (lane == 0) t = atomicAdd(p.queue, 1);
     t = __shfl(t, 0);
     if (t >= n_tiles) break;
-    build_tile<G, T, LW>(p, t);
+    build_tile<G, T, LW>(p, t, wl);
   }
 }
 

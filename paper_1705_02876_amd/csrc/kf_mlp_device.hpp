@@ -160,4 +160,74 @@ __device__ __forceinline__ void eval_wave(const unsigned char* packed, const flo
   }
 }
 
+// Forward weights staged in LDS for the builder: W1, W2, W3 operand tiles
+// (12288 bytes) then b1, b2, b3 (float), copied once per block.
+constexpr int kFwdTileBytes = kPkW2T;               // W1, W2, W3 tiles
+constexpr int kFwdBytes = kFwdTileBytes + 4 * (2 * kH + kOut);
+constexpr int kLdsB1 = kFwdTileBytes, kLdsB2 = kLdsB1 + 4 * kH, kLdsB3 = kLdsB2 + 4 * kH;
+
+// block-cooperative copy (all threads of the block, then a block barrier)
+__device__ __forceinline__ void stage_forward(const unsigned char* __restrict__ packed, unsigned char* lds) {
+  for (int i = threadIdx.x; i < kFwdTileBytes / 16; i += blockDim.x)
+    reinterpret_cast<uint4*>(lds)[i] = reinterpret_cast<const uint4*>(packed)[i];
+  for (int i = threadIdx.x; i < 2 * kH + kOut; i += blockDim.x)
+    reinterpret_cast<float*>(lds + kFwdTileBytes)[i] = reinterpret_cast<const float*>(packed + kPkB1)[i];
+  __syncthreads();
+}
+
+// eval_wave with the weights read from LDS right before each product, so that
+// only one record tile's activations are live at a time.
+__device__ __forceinline__ void eval_wave_lds(const unsigned char* lds, const float f[kIn], int lane, float& o0,
+                                              float& o1) {
+  const int g = lane >> 4, q = 4 * g;
+  const float* b1 = reinterpret_cast<const float*>(lds + kLdsB1);
+  const float* b2 = reinterpret_cast<const float*>(lds + kLdsB2);
+  const float* b3 = reinterpret_cast<const float*>(lds + kLdsB3);
+  o0 = 0.f;
+  o1 = 0.f;
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int t = 0; t < 4; ++t) {
+    int woff = 0;
+    asm volatile("" : "+v"(woff));  // keeps the weight reads inside this loop
+    const unsigned char* wl = lds + woff;
+    const int src = 16 * t + (lane & 15);
+    f32x4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float lo = __shfl(f[e], src);
+      const float hi = __shfl(f[4 + e], src);
+      v[e] = g == 0 ? lo : (g == 1 ? hi : 0.f);
+    }
+    const bf16x4 xb = to_bf16x4(v);
+    bf16x4 h1b[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 a = mfma(load_tile(wl, kPkW1, mt, lane), xb, z);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = fmaxf(a[e] + b1[16 * mt + q + e], 0.f);
+      h1b[mt] = to_bf16x4(a);
+    }
+    bf16x4 h2b[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 a = z;
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) a = mfma(load_tile(wl, kPkW2, mt * 4 + kt, lane), h1b[kt], a);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = fmaxf(a[e] + b2[16 * mt + q + e], 0.f);
+      h2b[mt] = to_bf16x4(a);
+    }
+    f32x4 o = z;
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) o = mfma(load_tile(wl, kPkW3, kt, lane), h2b[kt], o);
+    const float r0 = __shfl(o[0] + b3[0], lane & 15);
+    const float r1 = __shfl(o[1] + b3[1], lane & 15);
+    if (g == t) {
+      o0 = r0;
+      o1 = r1;
+    }
+  }
+}
+
 }  // namespace kfm
