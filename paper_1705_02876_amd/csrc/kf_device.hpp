@@ -43,14 +43,18 @@ struct Geom {
 
 constexpr int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
-// precision-generic math
-KF_DEV float rsqrt_t(float x) { return __frsqrt_rn(x); }
+// precision-generic math.  The float versions use the hardware approximations
+// (reciprocal, reciprocal square root, square root: about one ulp) instead of
+// the correctly rounded software sequences; double stays IEEE.
+KF_DEV float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 KF_DEV double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+KF_DEV float div_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+KF_DEV double div_t(double a, double b) { return a / b; }
 KF_DEV float atan_t(float x) { return atanf(x); }
 KF_DEV double atan_t(double x) { return atan(x); }
 KF_DEV float log_t(float x) { return logf(x); }
 KF_DEV double log_t(double x) { return log(x); }
-KF_DEV float sqrt_t(float x) { return sqrtf(x); }
+KF_DEV float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
 KF_DEV double sqrt_t(double x) { return sqrt(x); }
 KF_DEV float abs_t(float x) { return fabsf(x); }
 KF_DEV double abs_t(double x) { return fabs(x); }
@@ -95,8 +99,8 @@ KF_DEV int32_t helix_to_r(const T s[6], T a, T R, T zh, Prop<T>& o) {
   const T sq = sqrt_t(disc);
   // numerically stable roots of A w^2 + 2 au w - D/2 = 0
   const T qq = -(au + copysign_t(sq, au));
-  const T r1 = qq / A;
-  const T r2 = (T(-0.5) * D) / qq;
+  const T r1 = div_t(qq, A);
+  const T r2 = div_t(T(-0.5) * D, qq);
   T w = T(INFINITY);
   if (r1 > T(0)) w = r1;
   if (r2 > T(0) && r2 < w) w = r2;
@@ -105,10 +109,10 @@ KF_DEV int32_t helix_to_r(const T s[6], T a, T R, T zh, Prop<T>& o) {
   const T tau2 = tau * tau;
   // atan(tau) / tau, series near 0
   const T small = sizeof(T) == 4 ? T(1e-3) : T(1e-5);
-  const T at_over = (abs_t(tau) < small) ? (T(1) - tau2 * (T(1) / T(3)) + tau2 * tau2 * T(0.2)) : (atan_t(tau) / tau);
+  const T at_over = (abs_t(tau) < small) ? (T(1) - tau2 * (T(1) / T(3)) + tau2 * tau2 * T(0.2)) : div_t(atan_t(tau), tau);
   const T t = T(2) * w * at_over;
   const T phi = kap * t;
-  const T iden = T(1) / (T(1) + tau2);
+  const T iden = div_t(T(1), T(1) + tau2);
   const T sn = T(2) * tau * iden;
   const T cs = (T(1) - tau2) * iden;
   const T S = T(2) * w * iden;         // sin(phi) / kappa
@@ -144,7 +148,7 @@ KF_DEV int32_t helix_to_r(const T s[6], T a, T R, T zh, Prop<T>& o) {
   const T a44 = cs - pxn * py * fp2;
   // surface constraint: J = (I - v w^T) Jt
   const T v0 = pxn * ipt, v1 = pyn * ipt, v2 = pz * ipt, v3 = -kap * pyn, v4 = kap * pxn;
-  const T iden2 = T(1) / (xn * v0 + yn * v1);
+  const T iden2 = div_t(T(1), xn * v0 + yn * v1);
   const T w0 = xn * iden2, w1 = yn * iden2;
   const T w3 = w0 * a03 + w1 * a13;
   const T w4 = w0 * a04 + w1 * a14;
@@ -232,15 +236,15 @@ KF_DEV int32_t material(T s[6], T c[21], T xx0, T eloss, T mass) {
   const T u0 = s[3] * ip, u1 = s[4] * ip, u2 = s[5] * ip;
   const T ir = rsqrt_t(s[0] * s[0] + s[1] * s[1]);
   const T cospsi = abs_t((u0 * s[0] + u1 * s[1]) * ir);
-  const T tt = xx0 / cospsi;
+  const T tt = div_t(xx0, cospsi);
   const T m2 = mass * mass;
   const T E = sqrt_t(p2 + m2);
-  const T beta = p / E;
-  const T th0 = T(0.0136) / (beta * p) * sqrt_t(tt) * (T(1) + T(0.038) * log_t(tt / (beta * beta)));
+  const T beta = div_t(p, E);
+  const T th0 = div_t(T(0.0136), beta * p) * sqrt_t(tt) * (T(1) + T(0.038) * log_t(div_t(tt, beta * beta)));
   const T E2 = E - eloss * tt;
   if (!(E2 > mass)) return ST_STOPPED;
   const T pn = sqrt_t((E2 - mass) * (E2 + mass));
-  const T f = pn / p;
+  const T f = div_t(pn, p);
 #pragma unroll
   for (int i = 3; i < 6; ++i) s[i] *= f;
 #pragma unroll
@@ -270,7 +274,7 @@ KF_DEV bool inv3_packed(const T r[6], T ri[6]) {
   const T det = a * i00 + b * i10 + e * i20;
   const T m2 = a * d - b * b;
   if (!(a > T(0)) || !(m2 > T(0)) || !(det > T(0))) return false;
-  const T id = T(1) / det;
+  const T id = div_t(T(1), det);
   ri[0] = i00 * id;
   ri[1] = i10 * id;
   ri[2] = (a * g - e * e) * id;

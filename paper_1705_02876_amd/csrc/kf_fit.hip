@@ -127,9 +127,12 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
   load_track(state_in, cov_in, ld, i, s, c);
   const float qf = static_cast<float>(charge[i]);
   const T a = T(-static_cast<double>(charge[i]) * kCLight * g.bz);
-  int last = -1;
-  for (int l = 0; l < L; ++l)
-    if (hit_idx[l * ld_idx + i] >= 0) last = l;
+  int last = -1;  // last layer with a hit: searched from the outside in (most tracks end near the outer layers)
+  for (int l = L - 1; l >= 0; --l)
+    if (hit_idx[l * ld_idx + i] >= 0) {
+      last = l;
+      break;
+    }
   T chi2 = T(0);
   int32_t nh = 0, st = 0;
   if (res) {

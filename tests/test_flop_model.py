@@ -21,6 +21,9 @@ def _host_header(dst):
            'static inline float __frsqrt_rn(float x) { return 1.0f / std::sqrt(x); }\n')
     src = src.replace("#include <hip/hip_runtime.h>\n", pre, 1)
     src = src.replace("#define KF_DEV __device__ __forceinline__", "#define KF_DEV static inline")
+    src = src.replace("__builtin_amdgcn_rsqf(x)", "1.0f / std::sqrt(x)")
+    src = src.replace("__builtin_amdgcn_sqrtf(x)", "std::sqrt(x)")
+    src = src.replace("a * __builtin_amdgcn_rcpf(b)", "a / b")
     src = src.replace("__device__ __forceinline__", "static inline")
     src = src.replace("KF_DEV double copysign_t(double a, double b) { return copysign(a, b); }",
                       "KF_DEV double copysign_t(double a, double b) { return copysign(a, b); }\n"
@@ -29,7 +32,8 @@ def _host_header(dst):
                       "KF_DEV CF log_t(CF x) { cnt_log++; return CF::raw(std::log(x.v)); }\n"
                       "KF_DEV CF sqrt_t(CF x) { cnt_sqrt++; return CF::raw(std::sqrt(x.v)); }\n"
                       "KF_DEV CF abs_t(CF x) { return CF::raw(std::fabs(x.v)); }\n"
-                      "KF_DEV CF copysign_t(CF a, CF b) { return CF::raw(std::copysign(a.v, b.v)); }")
+                      "KF_DEV CF copysign_t(CF a, CF b) { return CF::raw(std::copysign(a.v, b.v)); }\n"
+                      "KF_DEV CF div_t(CF a, CF b) { return a / b; }")
     open(dst, "w").write(src)
 
 
