@@ -183,6 +183,21 @@ def cpu_baseline_build(prob, det32, max_seeds=300_000, N=6):
                       f"build N={N}, {cores} host threads (each bins the sample's hits), {dt:.2f} s wall"}
 
 
+def physics_leg(ctx, bp, seeds, hits, bins, bout, cfg):
+    """Efficiency and fake rate of the combinatorial build (the timed configuration) and of the best-hit
+    build (one candidate per seed) on the same events, judged against the simulation truth (untimed)."""
+    import torch
+    from paper_1705_02876_amd import judge, kfmi_build as KB
+    S_ = seeds["n"]
+    comb = judge.judge_problem(bp, bout["cand_hits"][:, :S_, 0].T.cpu().numpy())
+    c1 = KB.make_cfg(max_cands=1, mode=cfg.mode, precision=cfg.precision)
+    o1 = KB.build(ctx, c1, seeds, bins, hits["layer_offsets"], bp.n_events)
+    torch.cuda.synchronize()
+    best = judge.judge_problem(bp, o1["cand_hits"][:, :S_, 0].T.cpu().numpy())
+    pick = lambda r: {"eff": r["eff"], "fake_rate": r["fake_rate"], "eligible": r["n_eligible"]}
+    return {"combinatorial": dict(pick(comb), max_cands=int(cfg.max_cands)), "best_hit": pick(best)}
+
+
 def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, plain_build_ms):
     """Learned search window: residual records of the fit, full-batch training on the GPU, then the
     learned build timed like the plain one and both judged against the simulation truth."""
@@ -415,6 +430,7 @@ def main():
                            "updates": int(counters[4])},
         "fit_status_nonzero": int((stat != 0).sum().item()),
     }
+    out["physics"] = physics_leg(ctx, bp, seeds, hits, bins, bout, cfg)
     if not args.no_learned:
         out["learned_window"] = learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N,
                                             dict(state=st_in, cov=cv_in, q=q, hidx=hidx, hpos=hpos, hcov=hcov,
