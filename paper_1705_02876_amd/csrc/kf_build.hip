@@ -27,10 +27,12 @@ namespace {
 
 constexpr int kBinWaves = 16;
 constexpr int kBinThreads = kBinWaves * 64;
-constexpr int kMaxBins = 2048;
+constexpr int kMaxBins = 2048;         // per-wave histogram binning (bin_kernel)
+constexpr int kMaxBinsFine = 32768;    // one-histogram binning (bin_fine_kernel)
 constexpr uint32_t kHole = 0xFFFFFFu;
 constexpr int kScanUnroll = 4;                  // work items per lane and scan iteration
 constexpr int kQueueCap = 64 + 64 * kScanUnroll;  // box-passing (candidate, slot) pairs awaiting their chi2
+constexpr int kXcds = 8;                          // accelerator dies of the device (work-queue chunks)
 
 __device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, double zh, int n_phi, int n_eta) {
 #pragma clang fp contract(off)
@@ -182,6 +184,116 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
 
 #undef cnt
 
+// Binning for fine grids (more bins than the per-wave histograms hold): one
+// LDS histogram per (event, layer) with atomics, a block scan, an unordered
+// scatter of hit indices, then each bin's segment sorted by hit index (bins are
+// small), so the result is the same stable order as bin_kernel's.
+__global__ void __launch_bounds__(kBinThreads) bin_fine_kernel(int32_t L, const int64_t* __restrict__ layer_offsets,
+                                                               const float* __restrict__ hit_pos,
+                                                               const float* __restrict__ hit_cov, int64_t ldh,
+                                                               int32_t n_phi, int32_t n_eta, Geom g,
+                                                               int32_t* __restrict__ bins,
+                                                               int32_t* __restrict__ bin_offsets,
+                                                               int32_t* __restrict__ perm, float* __restrict__ binned,
+                                                               float* __restrict__ layer_vmax) {
+  extern __shared__ int32_t cnt_fine[];  // [nb] counts, then scatter cursors
+  __shared__ int32_t wsum[kBinWaves];
+  __shared__ uint32_t vmax_bits[2];
+  const int el = blockIdx.x;
+  const int l = el % L;
+  const int nb = n_phi * n_eta;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int64_t lo = layer_offsets[el], hi = layer_offsets[el + 1];
+  for (int i = tid; i < nb; i += kBinThreads) cnt_fine[i] = 0;
+  if (tid < 2) vmax_bits[tid] = 0u;
+  __syncthreads();
+  const double R = static_cast<double>(g.r[l]);
+  const double zh = static_cast<double>(g.z_half[l]);
+  float my_vxy = 0.f, my_vz = 0.f;
+  for (int64_t h = lo + tid; h < hi; h += kBinThreads) {
+    const int bin = hit_bin(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h], R, zh, n_phi, n_eta);
+    bins[h] = bin;
+    atomicAdd(&cnt_fine[bin], 1);
+    const float vxx = hit_cov[h], vyx = hit_cov[ldh + h], vyy = hit_cov[2 * ldh + h], vzz = hit_cov[5 * ldh + h];
+    const float d = 0.5f * (vxx - vyy);
+    my_vxy = fmaxf(my_vxy, 0.5f * (vxx + vyy) + sqrtf(d * d + vyx * vyx));
+    my_vz = fmaxf(my_vz, vzz);
+  }
+  atomicMax(&vmax_bits[0], __float_as_uint(my_vxy));
+  atomicMax(&vmax_bits[1], __float_as_uint(my_vz));
+  __syncthreads();
+  // exclusive scan of the counts: each wave a contiguous block of bins, then the waves' totals
+  const int per_w = (nb + kBinWaves - 1) / kBinWaves;
+  const int b0 = wave * per_w;
+  const int b1 = (b0 + per_w < nb) ? b0 + per_w : nb;
+  int wrun = 0;
+  for (int base = b0; base < b1; base += 64) {
+    const int bin = base + lane;
+    const int v = (bin < b1) ? cnt_fine[bin] : 0;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off);
+      if (lane >= off) x += y;
+    }
+    if (bin < b1) cnt_fine[bin] = wrun + x - v;
+    wrun += __shfl(x, 63);
+  }
+  if (lane == 0) wsum[wave] = wrun;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int w = 0; w < kBinWaves; ++w) {
+      const int c = wsum[w];
+      wsum[w] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  int32_t* bo = bin_offsets + static_cast<int64_t>(el) * (nb + 1);
+  for (int bin = tid; bin < nb; bin += kBinThreads) {
+    const int off = cnt_fine[bin] + wsum[bin / per_w];
+    cnt_fine[bin] = off;
+    bo[bin] = static_cast<int32_t>(lo + off);
+  }
+  if (tid == 0) {
+    bo[nb] = static_cast<int32_t>(hi);
+    layer_vmax[2 * el] = __uint_as_float(vmax_bits[0]);
+    layer_vmax[2 * el + 1] = __uint_as_float(vmax_bits[1]);
+  }
+  __syncthreads();
+  // unordered scatter of hit indices
+  for (int64_t h = lo + tid; h < hi; h += kBinThreads) {
+    const int at = atomicAdd(&cnt_fine[bins[h]], 1);
+    perm[lo + at] = static_cast<int32_t>(h);
+  }
+  __syncthreads();
+  // each bin's segment in hit-index order (insertion sort; a bin holds a few hits)
+  for (int bin = tid; bin < nb; bin += kBinThreads) {
+    const int64_t s0 = bo[bin], s1 = (bin + 1 < nb) ? static_cast<int64_t>(bo[bin + 1]) : hi;
+    for (int64_t i = s0 + 1; i < s1; ++i) {
+      const int32_t v = perm[i];
+      int64_t j = i - 1;
+      while (j >= s0 && perm[j] > v) {
+        perm[j + 1] = perm[j];
+        --j;
+      }
+      perm[j + 1] = v;
+    }
+  }
+  __syncthreads();
+  for (int64_t slot = lo + tid; slot < hi; slot += kBinThreads) {
+    const int64_t h = perm[slot];
+    float4* rec = reinterpret_cast<float4*>(binned + slot * KF_BINNED_FLOATS);
+    rec[0] = make_float4(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h],
+                         __int_as_float(static_cast<int32_t>(h - lo)));
+    rec[1] = make_float4(hit_cov[h], hit_cov[ldh + h], hit_cov[2 * ldh + h], hit_cov[3 * ldh + h]);
+    rec[2] = make_float4(hit_cov[4 * ldh + h], hit_cov[5 * ldh + h], 0.f, 0.f);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // building
 // ---------------------------------------------------------------------------
@@ -270,8 +382,10 @@ struct ScanLds {
   int32_t start[64]; // first slot of each candidate's range
   int32_t q_slot[kQueueCap];
   int32_t q_own[kQueueCap];
-  int32_t r_own[64], r_idx[64], r_slot[64];
+  int32_t r_idx[64], r_slot[64];
   T r_c2[64];
+  int32_t cnt[64], rstart[64];  // compatible results per candidate in a batch, and where they start
+  int32_t live_lane[64];        // compacted live candidates -> lane (window network)
 };
 
 // orders this lane's LDS accesses of the wave before and after (the wave executes in lockstep; this keeps the
@@ -368,7 +482,12 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
         for (int k = 0; k < 8; ++k) f[k] = 0.f;
       }
       float o0, o1;
-      kfm::eval_wave_lds(mlp_lds, f, lane, o0, o1);
+      const uint64_t um = __ballot(use);
+      const int pos = use ? __popcll(um & lanes_below) : -1;
+      wave_lds_sync();
+      if (use) C.live_lane[pos] = lane;
+      wave_lds_sync();
+      kfm::eval_compact_lds(mlp_lds, f, lane, C.live_lane, __popcll(um), pos, o0, o1);
       if (use) {
         lwt = p.nsigma * __expf(o0);
         lwz = p.nsigma * __expf(o1);
@@ -442,9 +561,10 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
         C.box[6][lane] = wz;
         const int nr = part ? 2 * (ie1 - ie0 + 1) : 0;
         const int max_nr = wave_max_i(nr);
-        for (int r = 0; r < max_nr; ++r) {
-          // this lane's r-th slot range
-          int ra = 0, rn = 0;
+        // bounds of this lane's r-th slot range (row ie0 + r/2, segment r%2)
+        auto range_of = [&](int r, int& ra, int& rn) {
+          ra = 0;
+          rn = 0;
           if (r < nr) {
             const int row = (ie0 + (r >> 1)) * p.n_phi;
             if ((r & 1) == 0) {
@@ -455,6 +575,13 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
               rn = bo[row + wrap_end] - ra;
             }
           }
+        };
+        int qn = 0;  // box-passing pairs queued, carried across the ranges of this pass
+        int nra = 0, nrn = 0;
+        range_of(0, nra, nrn);
+        for (int r = 0; r < max_nr; ++r) {
+          const int ra = nra, rn = nrn;
+          range_of(r + 1, nra, nrn);  // next range's bounds load while this one is scanned
           int incl = rn;
 #pragma unroll
           for (int o = 1; o < 64; o <<= 1) {
@@ -462,48 +589,51 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
             if (lane >= o) incl += y;
           }
           const int total = __shfl(incl, 63);
-          if (total == 0) continue;
-          wave_lds_sync();  // the previous range's readers are done with off/start
-          C.off[lane] = incl - rn;
-          C.start[lane] = ra;
-          wave_lds_sync();
-          int qn = 0;
-          for (int base = 0; base < total; base += 64 * kScanUnroll) {
-            int own[kScanUnroll], js[kScanUnroll];
-            float4 hv[kScanUnroll];
+          const bool last_range = r + 1 == max_nr;
+          if (total > 0) {
+            wave_lds_sync();  // the previous range's readers are done with off/start
+            C.off[lane] = incl - rn;
+            C.start[lane] = ra;
+            wave_lds_sync();
+          }
+          for (int base = 0; base < total || (last_range && base == 0); base += 64 * kScanUnroll) {
+            if (base < total) {
+              int own[kScanUnroll], js[kScanUnroll];
+              float4 hv[kScanUnroll];
 #pragma unroll
-            for (int u = 0; u < kScanUnroll; ++u) {
-              const int w = base + 64 * u + lane;
-              const int wc = w < total ? w : total - 1;
-              int lo = 0;  // largest candidate lane whose range starts at or before item wc
+              for (int u = 0; u < kScanUnroll; ++u) {
+                const int w = base + 64 * u + lane;
+                const int wc = w < total ? w : total - 1;
+                int lo = 0;  // largest candidate lane whose range starts at or before item wc
 #pragma unroll
-              for (int step = 32; step > 0; step >>= 1)
-                if (C.off[lo + step] <= wc) lo += step;
-              own[u] = lo;
-              js[u] = C.start[lo] + (wc - C.off[lo]);
-              hv[u] = recs[static_cast<int64_t>(js[u]) * 3];
-            }
-#pragma unroll
-            for (int u = 0; u < kScanUnroll; ++u) {
-              const int w = base + 64 * u + lane;
-              bool pass_box = false;
-              if (w < total) {
-                n_box++;
-                const int o = own[u];
-                const float dx = hv[u].x - C.box[0][o], dy = hv[u].y - C.box[1][o], dz = hv[u].z - C.box[2][o];
-                pass_box = fabsf(C.box[3][o] * dx + C.box[4][o] * dy) <= C.box[5][o] && fabsf(dz) <= C.box[6][o];
+                for (int step = 32; step > 0; step >>= 1)
+                  if (C.off[lo + step] <= wc) lo += step;
+                own[u] = lo;
+                js[u] = C.start[lo] + (wc - C.off[lo]);
+                hv[u] = recs[static_cast<int64_t>(js[u]) * 3];
               }
-              const uint64_t m = __ballot(pass_box);
-              if (pass_box) {
-                const int pos = qn + __popcll(m & lanes_below);
-                C.q_slot[pos] = js[u];
-                C.q_own[pos] = own[u];
+#pragma unroll
+              for (int u = 0; u < kScanUnroll; ++u) {
+                const int w = base + 64 * u + lane;
+                bool pass_box = false;
+                if (w < total) {
+                  n_box++;
+                  const int o = own[u];
+                  const float dx = hv[u].x - C.box[0][o], dy = hv[u].y - C.box[1][o], dz = hv[u].z - C.box[2][o];
+                  pass_box = fabsf(C.box[3][o] * dx + C.box[4][o] * dy) <= C.box[5][o] && fabsf(dz) <= C.box[6][o];
+                }
+                const uint64_t m = __ballot(pass_box);
+                if (pass_box) {
+                  const int pos = qn + __popcll(m & lanes_below);
+                  C.q_slot[pos] = js[u];
+                  C.q_own[pos] = own[u];
+                }
+                qn += __popcll(m);
               }
-              qn += __popcll(m);
             }
-            // evaluate full batches of 64 (and, after the last items of this range, the rest)
-            const bool range_done = base + 64 * kScanUnroll >= total;
-            while (qn >= 64 || (range_done && qn > 0)) {
+            // evaluate full batches of 64 (and, at the end of the pass, the rest)
+            const bool pass_done = last_range && base + 64 * kScanUnroll >= total;
+            while (qn >= 64 || (pass_done && qn > 0)) {
               wave_lds_sync();
               const int nb = qn < 64 ? qn : 64;
               bool comp = false;
@@ -536,12 +666,26 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
                   hidx = __float_as_int(h.w);
                 }
               }
-              const uint64_t rm = __ballot(comp);
-              const int nres = __popcll(rm);
-              wave_lds_sync();  // queue entries read; results may be written
+              // group the compatible results by candidate: per-candidate counts, their prefix, then each
+              // result at its candidate's start plus its rank (the insertion order does not matter: the
+              // top-N list orders by its key)
+              wave_lds_sync();  // queue entries read
+              C.cnt[lane] = 0;
+              wave_lds_sync();
+              const int rank = comp ? atomicAdd(&C.cnt[oq], 1) : 0;
+              wave_lds_sync();
+              const int count = C.cnt[lane];
+              int cinc = count;
+#pragma unroll
+              for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(cinc, o);
+                if (lane >= o) cinc += y;
+              }
+              const int first = cinc - count;
+              C.rstart[lane] = first;
+              wave_lds_sync();
               if (comp) {
-                const int rp = __popcll(rm & lanes_below);
-                C.r_own[rp] = oq;
+                const int rp = C.rstart[oq] + rank;
                 C.r_idx[rp] = hidx;
                 C.r_slot[rp] = jq;
                 C.r_c2[rp] = c2;
@@ -566,42 +710,27 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
               }
               qn = rest;
               wave_lds_sync();
-              if (nres > 0) {
-                // this lane's results are contiguous (the batch is in candidate order)
-                int lo = 0, hi = nres;
-                while (lo < hi) {
-                  const int mid = (lo + hi) >> 1;
-                  if (C.r_own[mid] < lane) lo = mid + 1; else hi = mid;
-                }
-                const int first = lo;
-                hi = nres;
-                while (lo < hi) {
-                  const int mid = (lo + hi) >> 1;
-                  if (C.r_own[mid] <= lane) lo = mid + 1; else hi = mid;
-                }
-                const int count = lo - first;
-                const int rounds = wave_max_i(count);
-                for (int k = 0; k < rounds; ++k) {
-                  if (k < count) {
-                    const int e = first + k;
-                    const T cc = C.r_c2[e];
-                    T nk = chi2 + (cc > T(0) ? cc : T(0));
-                    int32_t ni = C.r_idx[e];
-                    int32_t nj = C.r_slot[e];
+              const int rounds = wave_max_i(count);
+              for (int k = 0; k < rounds; ++k) {
+                if (k < count) {
+                  const int e = first + k;
+                  const T cc = C.r_c2[e];
+                  T nk = chi2 + (cc > T(0) ? cc : T(0));
+                  int32_t ni = C.r_idx[e];
+                  int32_t nj = C.r_slot[e];
 #pragma unroll
-                    for (int t = 0; t < G; ++t) {
-                      const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
-                      const T tk = lkey[t];
-                      const int32_t ti = lidx[t], tj = lslot[t];
-                      lkey[t] = sw ? nk : tk;
-                      lidx[t] = sw ? ni : ti;
-                      lslot[t] = sw ? nj : tj;
-                      nk = sw ? tk : nk;
-                      ni = sw ? ti : ni;
-                      nj = sw ? tj : nj;
-                    }
-                    cnt = cnt + 1 < N ? cnt + 1 : N;
+                  for (int t = 0; t < G; ++t) {
+                    const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
+                    const T tk = lkey[t];
+                    const int32_t ti = lidx[t], tj = lslot[t];
+                    lkey[t] = sw ? nk : tk;
+                    lidx[t] = sw ? ni : ti;
+                    lslot[t] = sw ? nj : tj;
+                    nk = sw ? tk : nk;
+                    ni = sw ? ti : ni;
+                    nj = sw ? tj : nj;
                   }
+                  cnt = cnt + 1 < N ? cnt + 1 : N;
                 }
               }
             }
@@ -623,6 +752,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       else if (hole_left)
         k = make_key(nhits, float(chi2), slot, kHole);
       const uint64_t kmin = group_min<G>(k);
+      if (__ballot(kmin != ~0ull) == 0) break;  // no seed of the wave has a child left
       const int winner = gbase + key_parent(kmin);
       const int32_t wslot = __shfl(has_hit ? lslot[0] : -1, winner);
       const T wchi2 = __shfl(has_hit ? lkey[0] : chi2, winner);
@@ -752,12 +882,20 @@ template <int G, typename T, bool LW>
 __global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t n_tiles) {
   const unsigned char* wl = MlpLds<LW>::stage(p.mlp);
   const int lane = threadIdx.x & 63;
-  for (;;) {
-    int32_t t = 0;
-    if (lane == 0) t = atomicAdd(p.queue, 1);
-    t = __shfl(t, 0);
-    if (t >= n_tiles) break;
-    build_tile<G, T, LW>(p, t, wl);
+  // The tile sequence is cut into kXcds contiguous chunks with a counter each.  Workgroups are dealt to the
+  // accelerator dies (XCDs) round robin, so a block takes tiles from the chunk of its die first, keeping each
+  // die's L2 on one stretch of events and directions, and then helps with the other chunks in turn.
+  const int home = static_cast<int>(blockIdx.x % kXcds);
+  for (int k = 0; k < kXcds; ++k) {
+    const int c = (home + k) % kXcds;
+    const int64_t lo = n_tiles * c / kXcds, hi = n_tiles * (c + 1) / kXcds;
+    for (;;) {
+      int32_t t = 0;
+      if (lane == 0) t = atomicAdd(&p.queue[c], 1);
+      t = __shfl(t, 0);
+      if (lo + t >= hi) break;
+      build_tile<G, T, LW>(p, lo + t, wl);
+    }
   }
 }
 
@@ -895,8 +1033,8 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
   if (!a) return set_error(KF_ERR_INVALID_ARG, "null args");
   if (!ctx->has_geometry) return set_error(KF_ERR_GEOMETRY, "no geometry set");
   if (a->n_events < 0 || a->ldh < 0) return set_error(KF_ERR_INVALID_ARG, "bad sizes");
-  if (a->n_phi < 1 || a->n_eta < 1 || a->n_phi * a->n_eta > kMaxBins)
-    return set_error(KF_ERR_INVALID_ARG, "need 1 <= n_phi * n_eta <= %d", kMaxBins);
+  if (a->n_phi < 1 || a->n_eta < 1 || static_cast<int64_t>(a->n_phi) * a->n_eta > kMaxBinsFine)
+    return set_error(KF_ERR_INVALID_ARG, "need 1 <= n_phi * n_eta <= %d", kMaxBinsFine);
   if (a->ldh >= (int64_t(1) << 31)) return set_error(KF_ERR_INVALID_ARG, "too many hits for int32 slots");
   if (a->n_events == 0) return KF_OK;
   if (!a->layer_offsets || !a->hit_pos || !a->hit_cov || !a->bin_offsets || !a->perm || !a->binned ||
@@ -907,16 +1045,29 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
   const int L = ctx->geom.n_layers;
   const int64_t n_el = a->n_events * L;
   if (n_el > INT32_MAX) return set_error(KF_ERR_INVALID_ARG, "too many (event, layer) pairs");
-  const size_t lds_bytes = static_cast<size_t>(kBinWaves + 1) * a->n_phi * a->n_eta * sizeof(int32_t);
-  if (int32_t rc = kfh::check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(bin_kernel),
+  const int nb = a->n_phi * a->n_eta;
+  if (nb <= kMaxBins) {
+    const size_t lds_bytes = static_cast<size_t>(kBinWaves + 1) * nb * sizeof(int32_t);
+    if (int32_t rc = kfh::check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(bin_kernel),
+                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                        static_cast<int>((kBinWaves + 1) * kMaxBins * sizeof(int32_t))),
+                                    "hipFuncSetAttribute(bin_kernel)"))
+      return rc;
+    bin_kernel<<<static_cast<unsigned>(n_el), kBinThreads, lds_bytes, kfh::stream_of(a->stream)>>>(
+        L, a->layer_offsets, a->hit_pos, a->hit_cov, a->ldh, a->n_phi, a->n_eta, ctx->dgeom,
+        static_cast<int32_t*>(a->workspace), a->bin_offsets, a->perm, a->binned, a->layer_vmax);
+    return kfh::check_hip(hipGetLastError(), "bin_kernel launch");
+  }
+  if (int32_t rc = kfh::check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(bin_fine_kernel),
                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                      static_cast<int>((kBinWaves + 1) * kMaxBins * sizeof(int32_t))),
-                                  "hipFuncSetAttribute(bin_kernel)"))
+                                                      static_cast<int>(kMaxBinsFine * sizeof(int32_t))),
+                                  "hipFuncSetAttribute(bin_fine_kernel)"))
     return rc;
-  bin_kernel<<<static_cast<unsigned>(n_el), kBinThreads, lds_bytes, kfh::stream_of(a->stream)>>>(
+  bin_fine_kernel<<<static_cast<unsigned>(n_el), kBinThreads, static_cast<size_t>(nb) * sizeof(int32_t),
+                    kfh::stream_of(a->stream)>>>(
       L, a->layer_offsets, a->hit_pos, a->hit_cov, a->ldh, a->n_phi, a->n_eta, ctx->dgeom,
       static_cast<int32_t*>(a->workspace), a->bin_offsets, a->perm, a->binned, a->layer_vmax);
-  return kfh::check_hip(hipGetLastError(), "bin_kernel launch");
+  return kfh::check_hip(hipGetLastError(), "bin_fine_kernel launch");
 }
 
 namespace {
@@ -939,7 +1090,7 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   const int L = ctx->geom.n_layers;
   if (cfg->max_cands < 1 || cfg->max_cands > 8) return set_error(KF_ERR_INVALID_ARG, "max_cands must be 1..8");
   if (!(cfg->chi2_cut > 0.f)) return set_error(KF_ERR_INVALID_ARG, "chi2_cut must be > 0");
-  if (cfg->n_phi < 1 || cfg->n_eta < 1 || cfg->n_phi * cfg->n_eta > kMaxBins)
+  if (cfg->n_phi < 1 || cfg->n_eta < 1 || static_cast<int64_t>(cfg->n_phi) * cfg->n_eta > kMaxBinsFine)
     return set_error(KF_ERR_INVALID_ARG, "bad bin counts");
   if (!(cfg->window_margin >= 0.f)) return set_error(KF_ERR_INVALID_ARG, "window_margin must be >= 0");
   if (cfg->mode != KF_BUILD_TILED && cfg->mode != KF_BUILD_PERSISTENT)
@@ -1037,7 +1188,7 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
     return kfh::check_hip(hipGetLastError(), "build_tiled_kernel launch");
   }
   p.queue = static_cast<int32_t*>(a->workspace);
-  fill_i32_kernel<<<1, 64, 0, stream>>>(p.queue, 1, 0);
+  fill_i32_kernel<<<1, 64, 0, stream>>>(p.queue, kXcds, 0);
   const int bpc = cfg->blocks_per_cu > 0 ? cfg->blocks_per_cu : 2;
   lc.persistent = true;
   lc.grid = static_cast<unsigned>(ctx->num_cus * bpc);

@@ -176,7 +176,69 @@ __device__ __forceinline__ void stage_forward(const unsigned char* __restrict__ 
 }
 
 // eval_wave with the weights read from LDS right before each product, so that
-// only one record tile's activations are live at a time.
+// only one record tile's activations are live at a time, and only for the
+// lanes that hold a record: `src` maps compacted record k < n to its lane (a
+// per-wave LDS table), `pos` is this lane's compacted index (or -1).  Tiles
+// past n records are skipped, so a wave with few live candidates pays for few
+// products.
+__device__ __forceinline__ void eval_compact_lds(const unsigned char* lds, const float f[kIn], int lane,
+                                                 const int32_t* src_lane, int n, int pos, float& o0, float& o1) {
+  const int g = lane >> 4, q = 4 * g;
+  const float* b1 = reinterpret_cast<const float*>(lds + kLdsB1);
+  const float* b2 = reinterpret_cast<const float*>(lds + kLdsB2);
+  const float* b3 = reinterpret_cast<const float*>(lds + kLdsB3);
+  o0 = 0.f;
+  o1 = 0.f;
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  const int tiles = (n + 15) >> 4;
+#pragma unroll 1
+  for (int t = 0; t < tiles; ++t) {
+    int woff = 0;
+    asm volatile("" : "+v"(woff));  // keeps the weight reads inside this loop
+    const unsigned char* wl = lds + woff;
+    const int k = 16 * t + (lane & 15);
+    const int src = k < n ? src_lane[k] : 0;
+    f32x4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float lo = __shfl(f[e], src);
+      const float hi = __shfl(f[4 + e], src);
+      v[e] = (k < n) ? (g == 0 ? lo : (g == 1 ? hi : 0.f)) : 0.f;
+    }
+    const bf16x4 xb = to_bf16x4(v);
+    bf16x4 h1b[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 a = mfma(load_tile(wl, kPkW1, mt, lane), xb, z);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = fmaxf(a[e] + b1[16 * mt + q + e], 0.f);
+      h1b[mt] = to_bf16x4(a);
+    }
+    bf16x4 h2b[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 a = z;
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) a = mfma(load_tile(wl, kPkW2, mt * 4 + kt, lane), h1b[kt], a);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = fmaxf(a[e] + b2[16 * mt + q + e], 0.f);
+      h2b[mt] = to_bf16x4(a);
+    }
+    f32x4 o = z;
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) o = mfma(load_tile(wl, kPkW3, kt, lane), h2b[kt], o);
+    // record 16 t + j's outputs sit in lane j; its owner has compacted index 16 t + j
+    const int from = pos >= 0 ? (pos & 15) : 0;
+    const float r0 = __shfl(o[0] + b3[0], from);
+    const float r1 = __shfl(o[1] + b3[1], from);
+    if (pos >= 0 && (pos >> 4) == t) {
+      o0 = r0;
+      o1 = r1;
+    }
+  }
+}
+
+// all 64 lanes hold a record
 __device__ __forceinline__ void eval_wave_lds(const unsigned char* lds, const float f[kIn], int lane, float& o0,
                                               float& o1) {
   const int g = lane >> 4, q = 4 * g;

@@ -115,6 +115,47 @@ def test_bin_hits_bit_exact(ctx, orc):
     assert np.allclose(vm[nonempty, 1], det.sigma_z ** 2, rtol=1e-5)
 
 
+@pytest.mark.parametrize("n_phi,n_eta", [(512, 32), (1024, 16), (37, 5)])
+def test_fine_bin_grids_bit_exact(ctx, orc, n_phi, n_eta):
+    """Grids beyond the per-wave histograms (up to 32768 bins) give the oracle's stable binning bit for bit."""
+    from paper_1705_02876_amd import kfmi_build as KB
+    print(f"[bin fine {n_phi}x{n_eta}]", flush=True)
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = S.make_build_problem([4000, 0, 9000, 12], det, 71)
+    ctx.kf_set_geometry(det32)
+    seeds, hits = KB.upload_problem(prob)
+    bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events, n_phi=n_phi, n_eta=n_eta)
+    g = orc.geometry(det32)
+    bo, perm, _ = orc.bin_hits(g, prob.n_events, prob.layer_hit_offsets, rounded(prob.hit_pos), n_phi=n_phi,
+                               n_eta=n_eta)
+    assert np.array_equal(bins["bin_offsets"].cpu().numpy(), bo)
+    assert np.array_equal(bins["perm"].cpu().numpy()[: perm.size].astype(np.int64), perm)
+    rec = bins["binned"].cpu().numpy()[: perm.size]
+    assert np.array_equal(rec[:, :3], np.asarray(prob.hit_pos, np.float32)[perm])
+
+
+@pytest.mark.parametrize("n_phi,n_eta,mode", [(512, 32, 1), (1024, 16, 0)])
+def test_build_independent_of_bin_grid(ctx, n_phi, n_eta, mode):
+    """The window bounds the chi2 region, so the candidates do not depend on the bin grid."""
+    import torch
+    from paper_1705_02876_amd import kfmi_build as KB
+    print(f"[build bins {n_phi}x{n_eta}]", flush=True)
+    det = S.detector_full()
+    ctx.kf_set_geometry(det.as_float32())
+    prob = S.make_build_problem([1500, 3000], det, 72)
+    seeds, hits = KB.upload_problem(prob)
+    res = []
+    for nphi, neta in ((64, 16), (n_phi, n_eta)):
+        bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events, n_phi=nphi, n_eta=neta)
+        out = KB.build(ctx, KB.make_cfg(n_phi=nphi, n_eta=neta, mode=mode, precision=KB.PREC_F32), seeds, bins,
+                       hits["layer_offsets"], prob.n_events)
+        torch.cuda.synchronize()
+        res.append({k: v.cpu().numpy() for k, v in out.items() if not k.startswith("_")})
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k], equal_nan=True), k
+
+
 @pytest.mark.parametrize("N,mode,precision", [(6, 0, 1), (6, 1, 1), (1, 0, 1), (3, 0, 1), (8, 1, 1), (6, 0, 0),
                                               (1, 1, 0)])
 def test_build_parity(ctx, orc, N, mode, precision):
