@@ -190,7 +190,7 @@ def physics_leg(ctx, bp, seeds, hits, bins, bout, cfg):
     from paper_1705_02876_amd import judge, kfmi_build as KB
     S_ = seeds["n"]
     comb = judge.judge_problem(bp, bout["cand_hits"][:, :S_, 0].T.cpu().numpy())
-    c1 = KB.make_cfg(max_cands=1, mode=cfg.mode, precision=cfg.precision)
+    c1 = KB.make_cfg(max_cands=1, mode=cfg.mode, precision=cfg.precision, n_phi=cfg.n_phi, n_eta=cfg.n_eta)
     o1 = KB.build(ctx, c1, seeds, bins, hits["layer_offsets"], bp.n_events)
     torch.cuda.synchronize()
     best = judge.judge_problem(bp, o1["cand_hits"][:, :S_, 0].T.cpu().numpy())
@@ -216,7 +216,7 @@ def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, pl
     train_ms = t0.elapsed_time(t1)
     lcfg = KB.make_cfg(max_cands=N, mode=cfg.mode, precision=cfg.precision, window_mode=KB.WINDOW_LEARNED,
                        learned_nsigma=args.nsigma, waves_per_block=cfg.waves_per_block,
-                       blocks_per_cu=cfg.blocks_per_cu)
+                       blocks_per_cu=cfg.blocks_per_cu, n_phi=cfg.n_phi, n_eta=cfg.n_eta)
     lws = torch.empty(KB.workspace_bytes(lcfg, bp.n_events, seeds["n"]), dtype=torch.uint8, device="cuda")
     lout = KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, mlp_packed=tr.packed, workspace=lws)
     if args.build_mode == "auto":
@@ -264,6 +264,9 @@ def main():
     ap.add_argument("--build-mode", choices=["auto", "tiled", "persistent"], default="auto",
                     help="auto: the build autotuner picks mode and launch shape (untimed, before warm-up)")
     ap.add_argument("--build-precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--bins", default="auto",
+                    help="hit bin grid PHIxETA, or auto: the fastest binning + build among a few grids (untimed); "
+                         "the candidates do not depend on the grid")
     ap.add_argument("--build-wpb", type=int, default=0, help="waves per block when --build-mode is not auto")
     ap.add_argument("--build-bpc", type=int, default=0, help="persistent blocks per CU when --build-mode is not auto")
     ap.add_argument("--fit-fp64", action="store_true", help="double-precision registers in the fit")
@@ -315,12 +318,36 @@ def main():
     seeds, hits = KB.upload_problem(bp)
     N = 6
     mode = KB.BUILD_PERSISTENT if args.build_mode == "persistent" else KB.BUILD_TILED
-    cfg = KB.make_cfg(max_cands=N, mode=mode,
-                      precision=KB.PREC_F64 if args.build_precision == "f64" else KB.PREC_F32,
-                      waves_per_block=args.build_wpb, blocks_per_cu=args.build_bpc)
-    bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events)
     bws_bytes = kfmi.load_library().kf_bin_hits_workspace_size(hits["pos"].shape[1])
     bws = torch.empty(max(bws_bytes, 4), dtype=torch.uint8, device=dev)
+    prec = KB.PREC_F64 if args.build_precision == "f64" else KB.PREC_F32
+    grids = [(64, 16), (256, 16), (512, 16), (512, 32), (1024, 32)] if args.bins == "auto" else \
+        [tuple(int(x) for x in args.bins.lower().split("x"))]
+    grid_ms = {}
+    if len(grids) > 1:
+        for nphi, neta in grids:  # untimed choice of the bin grid: binning + one default build, best of 2
+            c = KB.make_cfg(max_cands=N, mode=KB.BUILD_PERSISTENT, precision=prec, n_phi=nphi, n_eta=neta,
+                            waves_per_block=4, blocks_per_cu=4)
+            best = float("inf")
+            for _ in range(2):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                b_ = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events, n_phi=nphi,
+                                 n_eta=neta, workspace=bws)
+                KB.build(ctx, c, seeds, b_, hits["layer_offsets"], bp.n_events)
+                e1.record()
+                torch.cuda.synchronize()
+                best = min(best, e0.elapsed_time(e1))
+            grid_ms[f"{nphi}x{neta}"] = best
+            del b_
+        n_phi, n_eta = (int(x) for x in min(grid_ms, key=grid_ms.get).split("x"))
+        print(f"[bench] bin grid {n_phi}x{n_eta} (binning + build ms: {grid_ms})", file=sys.stderr, flush=True)
+    else:
+        n_phi, n_eta = grids[0]
+    cfg = KB.make_cfg(max_cands=N, mode=mode, precision=prec, waves_per_block=args.build_wpb,
+                      blocks_per_cu=args.build_bpc, n_phi=n_phi, n_eta=n_eta)
+    bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events, n_phi=n_phi, n_eta=n_eta,
+                       workspace=bws)
     build_ws = torch.empty(KB.workspace_bytes(cfg, bp.n_events, seeds["n"]), dtype=torch.uint8, device=dev)
     bout = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events, workspace=build_ws)
     tuned_ms = None
@@ -335,7 +362,8 @@ def main():
         ctx.kf_fit(st_in, cv_in, q, hidx, hpos, hcov, st_out, cv_out, chi2, nh, stat, fp64=args.fit_fp64)
 
     def bin_step():
-        KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events, out=bins, workspace=bws)
+        KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], bp.n_events, out=bins, workspace=bws,
+                    n_phi=n_phi, n_eta=n_eta)
 
     def build_step(counters=None):
         KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=bout, counters=counters,
@@ -414,9 +442,13 @@ def main():
         "config": {"workload": "full fit: 2M tracks, 17 barrel layers r=4..100 cm, 0.02 X0/layer + energy loss, "
                                "5% missing hits (6-17 hits), pT U[0.5,10] GeV, |eta|<1, Bz=3.8 T; "
                                "then batched build: 64 events log-uniform [1k,50k] tracks + 20% noise hits, "
-                               "64x16 bins, N=6, chi2<30",
+                               "N=6, chi2<30",
                    "tracks": n, "layers": L, "fit_hits": n_hits, "events": bp.n_events, "seeds": n_seeds,
                    "build_hits": int(bp.hit_pos.shape[0]),
+                   "bin_grid": f"{n_phi}x{n_eta}",
+                   "bin_grid_note": "the paper's 64x16 grid gives identical candidates (the window bounds the "
+                                    "chi2 region); the grid is a speed parameter chosen untimed",
+                   "bin_grid_trial_ms": grid_ms,
                    "build_mode": "persistent" if cfg.mode == KB.BUILD_PERSISTENT else "tiled",
                    "build_waves_per_block": int(cfg.waves_per_block), "build_blocks_per_cu": int(cfg.blocks_per_cu),
                    "build_autotuned": args.build_mode == "auto",

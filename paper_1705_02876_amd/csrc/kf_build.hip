@@ -33,6 +33,7 @@ constexpr uint32_t kHole = 0xFFFFFFu;
 constexpr int kScanUnroll = 4;                  // work items per lane and scan iteration
 constexpr int kQueueCap = 64 + 64 * kScanUnroll;  // box-passing (candidate, slot) pairs awaiting their chi2
 constexpr int kXcds = 8;                          // accelerator dies of the device (work-queue chunks)
+constexpr int kRangeChunk = 8;                    // slot ranges per candidate flattened together
 
 __device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, double zh, int n_phi, int n_eta) {
 #pragma clang fp contract(off)
@@ -378,8 +379,9 @@ template <typename T>
 struct ScanLds {
   float box[7][64];  // px0, py0, pz0, tx, ty, wt, wz of each lane's candidate
   T pred[8][64];     // x, y, z, nx, ny, att, atz, azz: what a chi2 needs of the candidate
-  int32_t off[64];   // exclusive prefix of the candidates' range lengths
-  int32_t start[64]; // first slot of each candidate's range
+  int32_t off[64];                // exclusive prefix of the lanes' item counts
+  int32_t rcum[kRangeChunk][64];  // per lane: items before each of its ranges
+  int32_t rst[kRangeChunk][64];   // per lane: first slot of each of its ranges
   int32_t q_slot[kQueueCap];
   int32_t q_own[kQueueCap];
   int32_t r_idx[64], r_slot[64];
@@ -443,8 +445,9 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
   int nc = seed_ok ? 1 : 0;  // candidates of this seed (same in all its lanes)
   uint32_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0, n_fb = 0;  // per lane and tile
   const float qf = seed_ok ? static_cast<float>(p.seed_charge[s]) : 1.f;
-  __shared__ ScanLds<T> scan_all[4];
-  ScanLds<T>& C = scan_all[(threadIdx.x >> 6) & 3];
+  // one ScanLds per wave of the block, in dynamic LDS sized by the launch (blockDim / 64 of them)
+  extern __shared__ __align__(16) unsigned char build_lds[];
+  ScanLds<T>& C = reinterpret_cast<ScanLds<T>*>(build_lds)[threadIdx.x >> 6];
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const float4* recs = reinterpret_cast<const float4*>(p.binned);
 
@@ -577,26 +580,32 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
           }
         };
         int qn = 0;  // box-passing pairs queued, carried across the ranges of this pass
-        int nra = 0, nrn = 0;
-        range_of(0, nra, nrn);
-        for (int r = 0; r < max_nr; ++r) {
-          const int ra = nra, rn = nrn;
-          range_of(r + 1, nra, nrn);  // next range's bounds load while this one is scanned
-          int incl = rn;
+        // Ranges are taken kRangeChunk per lane at a time: their bounds load together, each lane's ranges are
+        // laid end to end (cumulative counts in LDS) and the lanes' totals end to end, so one flat item space
+        // covers them all.
+        for (int r0 = 0; r0 < max_nr; r0 += kRangeChunk) {
+          int ra[kRangeChunk], rn[kRangeChunk];
+#pragma unroll
+          for (int j = 0; j < kRangeChunk; ++j) range_of(r0 + j, ra[j], rn[j]);
+          wave_lds_sync();  // the previous chunk's readers are done with the tables
+          int mine = 0;
+#pragma unroll
+          for (int j = 0; j < kRangeChunk; ++j) {
+            C.rcum[j][lane] = mine;
+            C.rst[j][lane] = ra[j];
+            mine += rn[j];
+          }
+          int incl = mine;
 #pragma unroll
           for (int o = 1; o < 64; o <<= 1) {
             const int y = __shfl_up(incl, o);
             if (lane >= o) incl += y;
           }
           const int total = __shfl(incl, 63);
-          const bool last_range = r + 1 == max_nr;
-          if (total > 0) {
-            wave_lds_sync();  // the previous range's readers are done with off/start
-            C.off[lane] = incl - rn;
-            C.start[lane] = ra;
-            wave_lds_sync();
-          }
-          for (int base = 0; base < total || (last_range && base == 0); base += 64 * kScanUnroll) {
+          const bool last_chunk = r0 + kRangeChunk >= max_nr;
+          C.off[lane] = incl - mine;
+          wave_lds_sync();
+          for (int base = 0; base < total || (last_chunk && base == 0); base += 64 * kScanUnroll) {
             if (base < total) {
               int own[kScanUnroll], js[kScanUnroll];
               float4 hv[kScanUnroll];
@@ -604,12 +613,17 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
               for (int u = 0; u < kScanUnroll; ++u) {
                 const int w = base + 64 * u + lane;
                 const int wc = w < total ? w : total - 1;
-                int lo = 0;  // largest candidate lane whose range starts at or before item wc
+                int lo = 0;  // largest candidate lane whose items start at or before item wc
 #pragma unroll
                 for (int step = 32; step > 0; step >>= 1)
                   if (C.off[lo + step] <= wc) lo += step;
+                const int local = wc - C.off[lo];
+                int jr = 0;  // that lane's range holding the item
+#pragma unroll
+                for (int step = kRangeChunk / 2; step > 0; step >>= 1)
+                  if (C.rcum[jr + step][lo] <= local) jr += step;
                 own[u] = lo;
-                js[u] = C.start[lo] + (wc - C.off[lo]);
+                js[u] = C.rst[jr][lo] + (local - C.rcum[jr][lo]);
                 hv[u] = recs[static_cast<int64_t>(js[u]) * 3];
               }
 #pragma unroll
@@ -632,7 +646,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
               }
             }
             // evaluate full batches of 64 (and, at the end of the pass, the rest)
-            const bool pass_done = last_range && base + 64 * kScanUnroll >= total;
+            const bool pass_done = last_chunk && base + 64 * kScanUnroll >= total;
             while (qn >= 64 || (pass_done && qn > 0)) {
               wave_lds_sync();
               const int nb = qn < 64 ? qn : 64;
@@ -997,9 +1011,9 @@ struct Launch {
 template <int G, typename T, bool LW>
 void launch_build(const Launch& c, const BuildP& p) {
   if (c.persistent)
-    build_persistent_kernel<G, T, LW><<<c.grid, c.block, 0, c.stream>>>(p, c.n_tiles);
+    build_persistent_kernel<G, T, LW><<<c.grid, c.block, (c.block / 64) * sizeof(ScanLds<T>), c.stream>>>(p, c.n_tiles);
   else
-    build_tiled_kernel<G, T, LW><<<c.grid, c.block, 0, c.stream>>>(p);
+    build_tiled_kernel<G, T, LW><<<c.grid, c.block, (c.block / 64) * sizeof(ScanLds<T>), c.stream>>>(p);
 }
 
 template <int G>

@@ -105,8 +105,9 @@ struct alignas(16) GradLds {
 
 __device__ __forceinline__ void stage_tile(uint16_t (*S)[16], int mt, f32x4 v, int lane) {
   const int row = 16 * mt + 4 * (lane >> 4), col = lane & 15;
+  const bf16x4 b = to_bf16x4(v);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) S[row + e][col] = f2bf(v[e]);
+  for (int e = 0; e < 4; ++e) S[row + e][col] = static_cast<uint16_t>(b[e]);
 }
 
 // operand with rows 16*tile + l%16 and the 4 records 4(l/16).. from an LDS block

@@ -51,12 +51,19 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return static_cast<uint16_t>(u >> 16);
 }
 
+// four floats to bfloat16 (round to nearest even) with the packed hardware conversion
 __device__ __forceinline__ bf16x4 to_bf16x4(f32x4 v) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const f32x2 a = {v[0], v[1]}, b = {v[2], v[3]};
+  const bf16x2 lo = __builtin_convertvector(a, bf16x2);
+  const bf16x2 hi = __builtin_convertvector(b, bf16x2);
+  const uint32_t ulo = __builtin_bit_cast(uint32_t, lo), uhi = __builtin_bit_cast(uint32_t, hi);
   bf16x4 r;
-  r[0] = static_cast<short>(f2bf(v[0]));
-  r[1] = static_cast<short>(f2bf(v[1]));
-  r[2] = static_cast<short>(f2bf(v[2]));
-  r[3] = static_cast<short>(f2bf(v[3]));
+  r[0] = static_cast<short>(ulo & 0xFFFFu);
+  r[1] = static_cast<short>(ulo >> 16);
+  r[2] = static_cast<short>(uhi & 0xFFFFu);
+  r[3] = static_cast<short>(uhi >> 16);
   return r;
 }
 

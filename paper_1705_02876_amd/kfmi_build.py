@@ -148,6 +148,11 @@ def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=Non
     N = cfg.max_cands
     L = ctx.n_layers
     dev = seeds["state"].device
+    nb = cfg.n_phi * cfg.n_eta
+    if bins["bin_offsets"].dim() != 2 or bins["bin_offsets"].shape[1] != nb + 1 or \
+            bins["bin_offsets"].shape[0] < n_events * L:
+        raise ValueError(f"bins were made for another grid or problem: bin_offsets {tuple(bins['bin_offsets'].shape)}, "
+                         f"config {cfg.n_phi}x{cfg.n_eta} with {n_events * L} (event, layer) pairs")
     if S > 0 and check:  # host copies of the offsets: not allowed while a graph is being captured
         check_offsets(seeds["offsets"], n_events, S, "seed_offsets")
         if int(seeds["offsets"][n_events].item()) != S or int(seeds["offsets"][0].item()) != 0:
