@@ -271,7 +271,7 @@ def main():
     ap.add_argument("--build-bpc", type=int, default=0, help="persistent blocks per CU when --build-mode is not auto")
     ap.add_argument("--fit-fp64", action="store_true", help="double-precision registers in the fit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-window leg")
-    ap.add_argument("--nsigma", type=float, default=4.0, help="learned window half width in network scales")
+    ap.add_argument("--nsigma", type=float, default=2.5, help="learned window half width in network scales")
     ap.add_argument("--train-tracks", type=int, default=625_000, help="fit tracks whose residuals train the window")
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--copy-probe", action="store_true",
@@ -326,8 +326,8 @@ def main():
     grid_ms = {}
     if len(grids) > 1:
         for nphi, neta in grids:  # untimed choice of the bin grid: binning + one default build, best of 2
-            c = KB.make_cfg(max_cands=N, mode=KB.BUILD_PERSISTENT, precision=prec, n_phi=nphi, n_eta=neta,
-                            waves_per_block=4, blocks_per_cu=4)
+            c = KB.make_cfg(max_cands=N, mode=KB.BUILD_TILED, precision=prec, n_phi=nphi, n_eta=neta,
+                            waves_per_block=1)
             best = float("inf")
             for _ in range(2):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -1,8 +1,8 @@
 """Build the gfx950 HIP library libkfmi.so in-tree with hipcc.
 
 Every .hip file under csrc/ is compiled for gfx950 with packed-FP32
-instruction selection disabled, then linked into one shared library next to
-this file.
+instruction selection disabled and multiply-add contraction limited to single
+expressions, then linked into one shared library next to this file.
 """
 import glob
 import os
@@ -15,8 +15,10 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkfmi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
+# -ffp-contract=on: multiply-adds are fused only within one source expression, so every inlined copy of a
+# function (and every kernel variant) rounds alike and the results do not depend on the launch shape.
+COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on", "-Xclang", "-target-feature",
+          "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
 
 def sources():

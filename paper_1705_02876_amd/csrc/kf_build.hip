@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "kf_internal.hpp"
 #include "kf_mlp_device.hpp"
@@ -32,8 +33,9 @@ constexpr int kMaxBinsFine = 32768;    // one-histogram binning (bin_fine_kernel
 constexpr uint32_t kHole = 0xFFFFFFu;
 constexpr int kScanUnroll = 4;                  // work items per lane and scan iteration
 constexpr int kQueueCap = 64 + 64 * kScanUnroll;  // box-passing (candidate, slot) pairs awaiting their chi2
+constexpr int kQueueDefer = 256;                  // learned window: pairs outside the learned box, deferred
 constexpr int kXcds = 8;                          // accelerator dies of the device (work-queue chunks)
-constexpr int kRangeChunk = 8;                    // slot ranges per candidate flattened together
+constexpr int kRangeChunk = 4;                    // slot ranges per candidate flattened together
 
 __device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, double zh, int n_phi, int n_eta) {
 #pragma clang fp contract(off)
@@ -375,19 +377,24 @@ __device__ __forceinline__ float wrap_pi(float a) {
 // candidate order within a range index; the queue is evaluated 64 pairs at a
 // time (one chi2 per lane) and each candidate then inserts its own compatible
 // hits, which are contiguous in the result list, into its register top-N.
-template <typename T>
+template <typename T, bool LW>
 struct ScanLds {
-  float box[7][64];  // px0, py0, pz0, tx, ty, wt, wz of each lane's candidate
-  T pred[8][64];     // x, y, z, nx, ny, att, atz, azz: what a chi2 needs of the candidate
+  T pred[8][64];     // x, y, z, nx, ny, att, atz, azz: what the box test and a chi2 need of the candidate
+  float box[2][64];  // plain window half widths wt, wz
   int32_t off[64];                // exclusive prefix of the lanes' item counts
   int32_t rcum[kRangeChunk][64];  // per lane: items before each of its ranges
   int32_t rst[kRangeChunk][64];   // per lane: first slot of each of its ranges
   int32_t q_slot[kQueueCap];
-  int32_t q_own[kQueueCap];
   int32_t r_idx[64], r_slot[64];
   T r_c2[64];
   int32_t cnt[64], rstart[64];  // compatible results per candidate in a batch, and where they start
   int32_t live_lane[64];        // compacted live candidates -> lane (window network)
+  uint8_t q_own[kQueueCap];     // owner lane of a queued pair; bit 6: outside the learned box
+  // learned window only (one element otherwise)
+  float lbox[2][LW ? 64 : 1];            // learned box half widths wt, wz
+  int32_t qb_slot[LW ? kQueueDefer : 1];  // pairs waiting for a fallback
+  int32_t need[LW ? 64 : 1];             // candidate (still) marked for the fallback
+  uint8_t qb_own[LW ? kQueueDefer : 1];
 };
 
 // orders this lane's LDS accesses of the wave before and after (the wave executes in lockstep; this keeps the
@@ -447,7 +454,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
   const float qf = seed_ok ? static_cast<float>(p.seed_charge[s]) : 1.f;
   // one ScanLds per wave of the block, in dynamic LDS sized by the launch (blockDim / 64 of them)
   extern __shared__ __align__(16) unsigned char build_lds[];
-  ScanLds<T>& C = reinterpret_cast<ScanLds<T>*>(build_lds)[threadIdx.x >> 6];
+  ScanLds<T, LW>& C = reinterpret_cast<ScanLds<T, LW>*>(build_lds)[threadIdx.x >> 6];
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const float4* recs = reinterpret_cast<const float4*>(p.binned);
 
@@ -473,29 +480,6 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       }
       n_steps++;
     }
-    // ---- learned window: one network evaluation per candidate, all lanes of the wave together
-    float lwt = INFINITY, lwz = INFINITY;
-    if (LW) {
-      const bool use = active && pstat == 0;
-      float f[8];
-      if (use) {
-        window_features(ps, pc, qf, p.g.r[l - 1], p.g.r[l], p.g.z_half[l], f);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) f[k] = 0.f;
-      }
-      float o0, o1;
-      const uint64_t um = __ballot(use);
-      const int pos = use ? __popcll(um & lanes_below) : -1;
-      wave_lds_sync();
-      if (use) C.live_lane[pos] = lane;
-      wave_lds_sync();
-      kfm::eval_compact_lds(mlp_lds, f, lane, C.live_lane, __popcll(um), pos, o0, o1);
-      if (use) {
-        lwt = p.nsigma * __expf(o0);
-        lwz = p.nsigma * __expf(o1);
-      }
-    }
     // ---- scan the window's bins, keep the best N children of this candidate
     T lkey[G];
     int32_t lidx[G], lslot[G];
@@ -505,13 +489,13 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       lidx[t] = 0x7FFFFFFF;
       lslot[t] = 0;
     }
-    int cnt = 0;
+    int cnt = 0;     // children in the list (at most N)
+    int cnt_in = 0;  // learned window: those inside the learned box (at most N)
     {
       // Window geometry of this lane's candidate (dead lanes only work for others).
       const bool live = active && pstat == 0;
       const float R = p.g.r[l];
       const LocalPred<T> lp = local_pred(ps, pc);
-      const float tx = float(lp.tx), ty = float(lp.ty);
       const float px0 = float(ps[0]), py0 = float(ps[1]), pz0 = float(ps[2]);
       const float rtt = live ? float(lp.att) + p.layer_vmax[2 * el] : 0.f;
       const float rzz = live ? float(pc[5]) + p.layer_vmax[2 * el + 1] : 0.f;
@@ -519,10 +503,44 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       // plain half widths bound the chi2 < cut region (Cauchy-Schwarz on R^-1)
       const float wt_plain = sqrtf(p.chi2_cut * rtt) * fac;
       const float wz_plain = sqrtf(p.chi2_cut * rzz) * fac;
+      // Learned window: one network evaluation per live candidate, all lanes of the wave together.  Its box
+      // (never wider than the plain one) decides which compatible hits count; when none is inside it, the
+      // compatible hits of the plain window count instead (fallback).  One scan of the plain window's bins
+      // serves both: pairs inside the learned box are evaluated at once, the other pairs inside the plain box
+      // wait in a second queue.  A candidate with no pair inside its learned box falls back for certain: its
+      // waiting pairs join the last batches of the scan.  One whose inside pairs all fail the cut (rare) takes
+      // them after it.
+      float wt_in = wt_plain, wz_in = wz_plain;
+      bool tighter = false;
+      if (LW) {
+        float f[8];
+        if (live) {
+          window_features(ps, pc, qf, p.g.r[l - 1], R, p.g.z_half[l], f);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) f[k] = 0.f;
+        }
+        float o0, o1;
+        const uint64_t um = __ballot(live);
+        const int lpos = live ? __popcll(um & lanes_below) : -1;
+        wave_lds_sync();
+        if (live) C.live_lane[lpos] = lane;
+        wave_lds_sync();
+        kfm::eval_compact_lds(mlp_lds, f, lane, C.live_lane, __popcll(um), lpos, o0, o1);
+        if (live) {
+          const float lwt = p.nsigma * __expf(o0);
+          const float lwz = p.nsigma * __expf(o1);
+          tighter = lwt < wt_plain || lwz < wz_plain;
+          wt_in = fminf(lwt, wt_plain);
+          wz_in = fminf(lwz, wz_plain);
+        }
+        C.lbox[0][lane] = wt_in;
+        C.lbox[1][lane] = wz_in;
+        C.need[lane] = tighter ? 1 : 0;  // cleared by the first pair inside the learned box
+      }
       const float php = atan2f(py0, px0);
       const float emax = asinhf(p.g.z_half[l] / R);
       const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
-      const bool tighter = live && (lwt < wt_plain || lwz < wz_plain);
       C.pred[0][lane] = ps[0];
       C.pred[1][lane] = ps[1];
       C.pred[2][lane] = ps[2];
@@ -531,225 +549,295 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       C.pred[5][lane] = lp.att;
       C.pred[6][lane] = lp.atz;
       C.pred[7][lane] = lp.azz;
-      // pass 0: learned box where it is tighter; pass 1: the plain window for every other live candidate
-      // and for those whose learned box held no compatible hit (fallback)
-      for (int pass = 0; pass < 2; ++pass) {
-        const bool part = pass == 0 ? tighter : (live && (!tighter || cnt == 0));
-        if (pass == 1 && tighter && cnt == 0) n_fb++;
-        if (__ballot(part) == 0) continue;
-        const float wt = pass == 0 ? fminf(lwt, wt_plain) : wt_plain;
-        const float wz = pass == 0 ? fminf(lwz, wz_plain) : wz_plain;
-        int ip0 = 0, nspan = p.n_phi, ie0 = 0, ie1 = -1;
-        if (part) {
-          const float sphi = wt / R;
-          if (sphi < 1.f) {
-            const float dphi = asinf(sphi);
-            if (dphi < 1.5707963f) {
-              ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
-              const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
-              nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
-            }
+      C.box[0][lane] = wt_plain;
+      C.box[1][lane] = wz_plain;
+      // bins the plain window overlaps: the cyclic phi interval [ip0, ip0 + nspan) and the eta rows ie0..ie1
+      int ip0 = 0, nspan = p.n_phi, ie0 = 0, ie1 = -1;
+      if (live) {
+        const float sphi = wt_plain / R;
+        if (sphi < 1.f) {
+          const float dphi = asinf(sphi);
+          if (dphi < 1.5707963f) {
+            ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
+            const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
+            nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
           }
-          ie0 = eta_bin_f(pz0 - wz, R, emax, p.n_eta);
-          ie1 = eta_bin_f(pz0 + wz, R, emax, p.n_eta);
         }
-        const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
-        const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
-        C.box[0][lane] = px0;
-        C.box[1][lane] = py0;
-        C.box[2][lane] = pz0;
-        C.box[3][lane] = tx;
-        C.box[4][lane] = ty;
-        C.box[5][lane] = wt;
-        C.box[6][lane] = wz;
-        const int nr = part ? 2 * (ie1 - ie0 + 1) : 0;
-        const int max_nr = wave_max_i(nr);
-        // bounds of this lane's r-th slot range (row ie0 + r/2, segment r%2)
-        auto range_of = [&](int r, int& ra, int& rn) {
-          ra = 0;
-          rn = 0;
-          if (r < nr) {
-            const int row = (ie0 + (r >> 1)) * p.n_phi;
-            if ((r & 1) == 0) {
-              ra = bo[row + ip0];
-              rn = bo[row + first_end] - ra;
-            } else if (wrap_end > 0) {
-              ra = bo[row];
-              rn = bo[row + wrap_end] - ra;
+        ie0 = eta_bin_f(pz0 - wz_plain, R, emax, p.n_eta);
+        ie1 = eta_bin_f(pz0 + wz_plain, R, emax, p.n_eta);
+      }
+      const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
+      const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
+      const int nr = live ? 2 * (ie1 - ie0 + 1) : 0;
+      const int max_nr = wave_max_i(nr);
+      // bounds of this lane's r-th slot range (row ie0 + r/2, segment r%2)
+      auto range_of = [&](int r, int& ra, int& rn) {
+        ra = 0;
+        rn = 0;
+        if (r < nr) {
+          const int row = (ie0 + (r >> 1)) * p.n_phi;
+          if ((r & 1) == 0) {
+            ra = bo[row + ip0];
+            rn = bo[row + first_end] - ra;
+          } else if (wrap_end > 0) {
+            ra = bo[row];
+            rn = bo[row + wrap_end] - ra;
+          }
+        }
+      };
+      int qn = 0;  // pairs awaiting their chi2, carried across the ranges
+      int qb = 0;  // learned window: pairs inside the plain box but outside the learned one, waiting
+      // Evaluates the queue 64 pairs at a time (all of it when final) and inserts the compatible hits into the
+      // owners' lists.  A queued owner with bit 6 set marks a pair outside the learned box: its hit is flagged
+      // (bit 30 of the index) and ranks after every unflagged hit of the list.
+      auto flush = [&](bool final_batch) {
+        while (qn >= 64 || (final_batch && qn > 0)) {
+          wave_lds_sync();
+          const int nb = qn < 64 ? qn : 64;
+          bool comp = false;
+          T c2 = T(0);
+          int32_t hidx = 0, jq = 0, oq = 0;
+          if (lane < nb) {
+            jq = C.q_slot[lane];
+            const int qo = C.q_own[lane];
+            oq = qo & 63;
+            const float4 h = recs[static_cast<int64_t>(jq) * 3];
+            const float4 c0 = recs[static_cast<int64_t>(jq) * 3 + 1];
+            const float4 c1 = recs[static_cast<int64_t>(jq) * 3 + 2];
+            const float mm[3] = {h.x, h.y, h.z};
+            const float vv[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
+            T pos3[6];
+            pos3[0] = C.pred[0][oq];
+            pos3[1] = C.pred[1][oq];
+            pos3[2] = C.pred[2][oq];
+            LocalPred<T> L;
+            L.nx = C.pred[3][oq];
+            L.ny = C.pred[4][oq];
+            L.tx = -L.ny;
+            L.ty = L.nx;
+            L.att = C.pred[5][oq];
+            L.atz = C.pred[6][oq];
+            L.azz = C.pred[7][oq];
+            n_chi2++;
+            if (!chi2_on_layer(pos3, L, mm, vv, c2) && c2 < T(p.chi2_cut)) {
+              comp = true;
+              n_comp++;
+              hidx = __float_as_int(h.w) | (LW ? ((qo >> 6) << 30) : 0);
             }
           }
-        };
-        int qn = 0;  // box-passing pairs queued, carried across the ranges of this pass
-        // Ranges are taken kRangeChunk per lane at a time: their bounds load together, each lane's ranges are
-        // laid end to end (cumulative counts in LDS) and the lanes' totals end to end, so one flat item space
-        // covers them all.
-        for (int r0 = 0; r0 < max_nr; r0 += kRangeChunk) {
-          int ra[kRangeChunk], rn[kRangeChunk];
-#pragma unroll
-          for (int j = 0; j < kRangeChunk; ++j) range_of(r0 + j, ra[j], rn[j]);
-          wave_lds_sync();  // the previous chunk's readers are done with the tables
-          int mine = 0;
-#pragma unroll
-          for (int j = 0; j < kRangeChunk; ++j) {
-            C.rcum[j][lane] = mine;
-            C.rst[j][lane] = ra[j];
-            mine += rn[j];
-          }
-          int incl = mine;
+          // group the compatible results by candidate: per-candidate counts, their prefix, then each
+          // result at its candidate's start plus its rank (the insertion order does not matter: the
+          // top-N list orders by its key)
+          wave_lds_sync();  // queue entries read
+          C.cnt[lane] = 0;
+          wave_lds_sync();
+          const int rank = comp ? atomicAdd(&C.cnt[oq], 1) : 0;
+          wave_lds_sync();
+          const int count = C.cnt[lane];
+          int cinc = count;
 #pragma unroll
           for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
+            const int y = __shfl_up(cinc, o);
+            if (lane >= o) cinc += y;
           }
-          const int total = __shfl(incl, 63);
-          const bool last_chunk = r0 + kRangeChunk >= max_nr;
-          C.off[lane] = incl - mine;
+          const int first = cinc - count;
+          C.rstart[lane] = first;
           wave_lds_sync();
-          for (int base = 0; base < total || (last_chunk && base == 0); base += 64 * kScanUnroll) {
-            if (base < total) {
-              int own[kScanUnroll], js[kScanUnroll];
-              float4 hv[kScanUnroll];
+          if (comp) {
+            const int rp = C.rstart[oq] + rank;
+            C.r_idx[rp] = hidx;
+            C.r_slot[rp] = jq;
+            C.r_c2[rp] = c2;
+          }
+          // move the unevaluated rest of the queue to its front
+          const int rest = qn - nb;
+          int keep_s[kScanUnroll + 1], keep_o[kScanUnroll + 1];
 #pragma unroll
-              for (int u = 0; u < kScanUnroll; ++u) {
-                const int w = base + 64 * u + lane;
-                const int wc = w < total ? w : total - 1;
-                int lo = 0;  // largest candidate lane whose items start at or before item wc
+          for (int u = 0; u <= kScanUnroll; ++u) {
+            const int from = nb + 64 * u + lane;
+            keep_s[u] = from < qn ? C.q_slot[from] : 0;
+            keep_o[u] = from < qn ? C.q_own[from] : 0;
+          }
+          wave_lds_sync();
 #pragma unroll
-                for (int step = 32; step > 0; step >>= 1)
-                  if (C.off[lo + step] <= wc) lo += step;
-                const int local = wc - C.off[lo];
-                int jr = 0;  // that lane's range holding the item
-#pragma unroll
-                for (int step = kRangeChunk / 2; step > 0; step >>= 1)
-                  if (C.rcum[jr + step][lo] <= local) jr += step;
-                own[u] = lo;
-                js[u] = C.rst[jr][lo] + (local - C.rcum[jr][lo]);
-                hv[u] = recs[static_cast<int64_t>(js[u]) * 3];
-              }
-#pragma unroll
-              for (int u = 0; u < kScanUnroll; ++u) {
-                const int w = base + 64 * u + lane;
-                bool pass_box = false;
-                if (w < total) {
-                  n_box++;
-                  const int o = own[u];
-                  const float dx = hv[u].x - C.box[0][o], dy = hv[u].y - C.box[1][o], dz = hv[u].z - C.box[2][o];
-                  pass_box = fabsf(C.box[3][o] * dx + C.box[4][o] * dy) <= C.box[5][o] && fabsf(dz) <= C.box[6][o];
-                }
-                const uint64_t m = __ballot(pass_box);
-                if (pass_box) {
-                  const int pos = qn + __popcll(m & lanes_below);
-                  C.q_slot[pos] = js[u];
-                  C.q_own[pos] = own[u];
-                }
-                qn += __popcll(m);
-              }
+          for (int u = 0; u <= kScanUnroll; ++u) {
+            const int to = 64 * u + lane;
+            if (to < rest) {
+              C.q_slot[to] = keep_s[u];
+              C.q_own[to] = static_cast<uint8_t>(keep_o[u]);
             }
-            // evaluate full batches of 64 (and, at the end of the pass, the rest)
-            const bool pass_done = last_chunk && base + 64 * kScanUnroll >= total;
-            while (qn >= 64 || (pass_done && qn > 0)) {
-              wave_lds_sync();
-              const int nb = qn < 64 ? qn : 64;
-              bool comp = false;
-              T c2 = T(0);
-              int32_t hidx = 0, jq = 0, oq = 0;
-              if (lane < nb) {
-                jq = C.q_slot[lane];
-                oq = C.q_own[lane];
-                const float4 h = recs[static_cast<int64_t>(jq) * 3];
-                const float4 c0 = recs[static_cast<int64_t>(jq) * 3 + 1];
-                const float4 c1 = recs[static_cast<int64_t>(jq) * 3 + 2];
-                const float mm[3] = {h.x, h.y, h.z};
-                const float vv[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
-                T pos3[6];
-                pos3[0] = C.pred[0][oq];
-                pos3[1] = C.pred[1][oq];
-                pos3[2] = C.pred[2][oq];
-                LocalPred<T> L;
-                L.nx = C.pred[3][oq];
-                L.ny = C.pred[4][oq];
-                L.tx = -L.ny;
-                L.ty = L.nx;
-                L.att = C.pred[5][oq];
-                L.atz = C.pred[6][oq];
-                L.azz = C.pred[7][oq];
-                n_chi2++;
-                if (!chi2_on_layer(pos3, L, mm, vv, c2) && c2 < T(p.chi2_cut)) {
-                  comp = true;
-                  n_comp++;
-                  hidx = __float_as_int(h.w);
+          }
+          qn = rest;
+          wave_lds_sync();
+          const int rounds = wave_max_i(count);
+          for (int k = 0; k < rounds; ++k) {
+            if (k < count) {
+              const int e = first + k;
+              const T cc = C.r_c2[e];
+              T nk = chi2 + (cc > T(0) ? cc : T(0));
+              int32_t ni = C.r_idx[e];
+              int32_t nj = C.r_slot[e];
+              if (LW && (ni >> 30) == 0) cnt_in = cnt_in + 1 < N ? cnt_in + 1 : N;
+#pragma unroll
+              for (int t = 0; t < G; ++t) {
+                bool sw;
+                if (LW) {
+                  const int fn = ni >> 30, ft = lidx[t] >> 30;
+                  sw = (t < N) && (fn < ft || (fn == ft && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]))));
+                } else {
+                  sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
                 }
+                const T tk = lkey[t];
+                const int32_t ti = lidx[t], tj = lslot[t];
+                lkey[t] = sw ? nk : tk;
+                lidx[t] = sw ? ni : ti;
+                lslot[t] = sw ? nj : tj;
+                nk = sw ? tk : nk;
+                ni = sw ? ti : ni;
+                nj = sw ? tj : nj;
               }
-              // group the compatible results by candidate: per-candidate counts, their prefix, then each
-              // result at its candidate's start plus its rank (the insertion order does not matter: the
-              // top-N list orders by its key)
-              wave_lds_sync();  // queue entries read
-              C.cnt[lane] = 0;
-              wave_lds_sync();
-              const int rank = comp ? atomicAdd(&C.cnt[oq], 1) : 0;
-              wave_lds_sync();
-              const int count = C.cnt[lane];
-              int cinc = count;
-#pragma unroll
-              for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(cinc, o);
-                if (lane >= o) cinc += y;
-              }
-              const int first = cinc - count;
-              C.rstart[lane] = first;
-              wave_lds_sync();
-              if (comp) {
-                const int rp = C.rstart[oq] + rank;
-                C.r_idx[rp] = hidx;
-                C.r_slot[rp] = jq;
-                C.r_c2[rp] = c2;
-              }
-              // move the unevaluated rest of the queue to its front
-              const int rest = qn - nb;
-              int keep_s[kScanUnroll + 1], keep_o[kScanUnroll + 1];
-#pragma unroll
-              for (int u = 0; u <= kScanUnroll; ++u) {
-                const int from = nb + 64 * u + lane;
-                keep_s[u] = from < qn ? C.q_slot[from] : 0;
-                keep_o[u] = from < qn ? C.q_own[from] : 0;
-              }
-              wave_lds_sync();
-#pragma unroll
-              for (int u = 0; u <= kScanUnroll; ++u) {
-                const int to = 64 * u + lane;
-                if (to < rest) {
-                  C.q_slot[to] = keep_s[u];
-                  C.q_own[to] = keep_o[u];
-                }
-              }
-              qn = rest;
-              wave_lds_sync();
-              const int rounds = wave_max_i(count);
-              for (int k = 0; k < rounds; ++k) {
-                if (k < count) {
-                  const int e = first + k;
-                  const T cc = C.r_c2[e];
-                  T nk = chi2 + (cc > T(0) ? cc : T(0));
-                  int32_t ni = C.r_idx[e];
-                  int32_t nj = C.r_slot[e];
-#pragma unroll
-                  for (int t = 0; t < G; ++t) {
-                    const bool sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
-                    const T tk = lkey[t];
-                    const int32_t ti = lidx[t], tj = lslot[t];
-                    lkey[t] = sw ? nk : tk;
-                    lidx[t] = sw ? ni : ti;
-                    lslot[t] = sw ? nj : tj;
-                    nk = sw ? tk : nk;
-                    ni = sw ? ti : ni;
-                    nj = sw ? tj : nj;
-                  }
-                  cnt = cnt + 1 < N ? cnt + 1 : N;
-                }
-              }
+              cnt = cnt + 1 < N ? cnt + 1 : N;
             }
           }
         }
+      };
+      // Appends the waiting pairs whose owner is marked in C.need to the queue, flagged as outside the learned
+      // box (the queue holds them: at most 63 + kQueueDefer pairs).
+      auto take_waiting = [&]() {
+        wave_lds_sync();
+        for (int b0 = 0; b0 < qb; b0 += 64) {
+          const int i = b0 + lane;
+          int jb = 0, ob = 0;
+          bool take = false;
+          if (i < qb) {
+            jb = C.qb_slot[i];
+            ob = C.qb_own[i];
+            take = C.need[ob] != 0;
+          }
+          const uint64_t mt = __ballot(take);
+          if (take) {
+            const int pos = qn + __popcll(mt & lanes_below);
+            C.q_slot[pos] = jb;
+            C.q_own[pos] = static_cast<uint8_t>(ob | 64);
+          }
+          qn += __popcll(mt);
+        }
+      };
+      // Ranges are taken kRangeChunk per lane at a time: their bounds load together, each lane's ranges are
+      // laid end to end (cumulative counts in LDS) and the lanes' totals end to end, so one flat item space
+      // covers them all.
+      for (int r0 = 0; r0 < max_nr; r0 += kRangeChunk) {
+        int ra[kRangeChunk], rn[kRangeChunk];
+#pragma unroll
+        for (int j = 0; j < kRangeChunk; ++j) range_of(r0 + j, ra[j], rn[j]);
+        wave_lds_sync();  // the previous chunk's readers are done with the tables
+        int mine = 0;
+#pragma unroll
+        for (int j = 0; j < kRangeChunk; ++j) {
+          C.rcum[j][lane] = mine;
+          C.rst[j][lane] = ra[j];
+          mine += rn[j];
+        }
+        int incl = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(incl, o);
+          if (lane >= o) incl += y;
+        }
+        const int total = __shfl(incl, 63);
+        C.off[lane] = incl - mine;
+        wave_lds_sync();
+        for (int base = 0; base < total; base += 64 * kScanUnroll) {
+          int own[kScanUnroll], js[kScanUnroll];
+          float4 hv[kScanUnroll];
+#pragma unroll
+          for (int u = 0; u < kScanUnroll; ++u) {
+            const int w = base + 64 * u + lane;
+            const int wc = w < total ? w : total - 1;
+            int lo = 0;  // largest candidate lane whose items start at or before item wc
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+              if (C.off[lo + step] <= wc) lo += step;
+            const int local = wc - C.off[lo];
+            int jr = 0;  // that lane's range holding the item
+#pragma unroll
+            for (int step = kRangeChunk / 2; step > 0; step >>= 1)
+              if (C.rcum[jr + step][lo] <= local) jr += step;
+            own[u] = lo;
+            js[u] = C.rst[jr][lo] + (local - C.rcum[jr][lo]);
+            hv[u] = recs[static_cast<int64_t>(js[u]) * 3];
+          }
+#pragma unroll
+          for (int u = 0; u < kScanUnroll; ++u) {
+            const int w = base + 64 * u + lane;
+            bool in_box = false, out_box = false;
+            if (w < total) {
+              n_box++;
+              const int o = own[u];
+              // tangent (-ny, nx) at the prediction
+              const float dx = hv[u].x - float(C.pred[0][o]), dy = hv[u].y - float(C.pred[1][o]);
+              const float az = fabsf(hv[u].z - float(C.pred[2][o]));
+              const float at = fabsf(-float(C.pred[4][o]) * dx + float(C.pred[3][o]) * dy);
+              const bool plain_box = at <= C.box[0][o] && az <= C.box[1][o];
+              if (LW) {
+                in_box = at <= C.lbox[0][o] && az <= C.lbox[1][o];
+                out_box = !in_box && plain_box;
+                if (in_box) C.need[o] = 0;
+              } else {
+                in_box = plain_box;
+              }
+            }
+            bool to_q = in_box;
+            int flag = 0;
+            if (LW) {
+              const uint64_t mo = __ballot(out_box);
+              const int no = __popcll(mo);
+              if (qb + no <= kQueueDefer) {
+                if (out_box) {
+                  const int pos = qb + __popcll(mo & lanes_below);
+                  C.qb_slot[pos] = js[u];
+                  C.qb_own[pos] = static_cast<uint8_t>(own[u]);
+                }
+                qb += no;
+              } else {
+                // waiting queue full: evaluate these pairs now, flagged as outside the learned box
+                to_q = in_box || out_box;
+                flag = out_box ? 64 : 0;
+              }
+            }
+            const uint64_t m = __ballot(to_q);
+            if (to_q) {
+              const int pos = qn + __popcll(m & lanes_below);
+              C.q_slot[pos] = js[u];
+              C.q_own[pos] = static_cast<uint8_t>(own[u] | flag);
+            }
+            qn += __popcll(m);
+          }
+          flush(false);  // full batches of 64
+        }
+      }
+      // candidates without any pair inside their learned box fall back for certain: their waiting pairs join the
+      // last batches
+      if (LW && qb > 0) take_waiting();
+      flush(true);
+      if (LW) {
+        const bool need = tighter && cnt_in == 0;
+        if (need) n_fb++;
+        if (qb > 0) {
+          // the rest of the fallbacks: candidates whose pairs inside the learned box all failed the cut
+          wave_lds_sync();
+          const bool late = need && C.need[lane] == 0;
+          if (__ballot(late) != 0) {
+            wave_lds_sync();
+            C.need[lane] = late ? 1 : 0;
+            take_waiting();
+            flush(true);
+          }
+        }
+        // a candidate with a compatible hit inside its learned box keeps only those (they rank first)
+        if (cnt_in > 0) cnt = cnt_in;
+#pragma unroll
+        for (int t = 0; t < G; ++t) lidx[t] &= 0x3FFFFFFF;
       }
     }
     // ---- merge the seed's lists: N rounds of a G-lane minimum of the rank key
@@ -886,31 +974,61 @@ struct MlpLds<true> {
 };
 
 template <int G, typename T, bool LW>
-__global__ void __launch_bounds__(256) build_tiled_kernel(BuildP p) {
+__device__ __forceinline__ void tiled_body(const BuildP& p) {
   const unsigned char* wl = MlpLds<LW>::stage(p.mlp);
   const int64_t tile = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   build_tile<G, T, LW>(p, tile, wl);
 }
 
 template <int G, typename T, bool LW>
-__global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t n_tiles) {
+__device__ __forceinline__ void persistent_body(const BuildP& p, int64_t n_tiles) {
   const unsigned char* wl = MlpLds<LW>::stage(p.mlp);
   const int lane = threadIdx.x & 63;
   // The tile sequence is cut into kXcds contiguous chunks with a counter each.  Workgroups are dealt to the
   // accelerator dies (XCDs) round robin, so a block takes tiles from the chunk of its die first, keeping each
   // die's L2 on one stretch of events and directions, and then helps with the other chunks in turn.
+  // (one loop with a single call site of the tile body, so that the body is inlined once)
   const int home = static_cast<int>(blockIdx.x % kXcds);
-  for (int k = 0; k < kXcds; ++k) {
-    const int c = (home + k) % kXcds;
-    const int64_t lo = n_tiles * c / kXcds, hi = n_tiles * (c + 1) / kXcds;
-    for (;;) {
-      int32_t t = 0;
-      if (lane == 0) t = atomicAdd(&p.queue[c], 1);
-      t = __shfl(t, 0);
-      if (lo + t >= hi) break;
+  int k = 0, c = home;
+  int64_t lo = n_tiles * c / kXcds, hi = n_tiles * (c + 1) / kXcds;
+#pragma unroll 1
+  for (;;) {
+    int32_t t = 0;
+    if (lane == 0) t = atomicAdd(&p.queue[c], 1);
+    t = __shfl(t, 0);
+    if (lo + t < hi) {
       build_tile<G, T, LW>(p, lo + t, wl);
+      continue;
     }
+    if (++k == kXcds) break;  // every chunk is exhausted
+    c = (home + k) % kXcds;
+    lo = n_tiles * c / kXcds;
+    hi = n_tiles * (c + 1) / kXcds;
   }
+}
+
+// Entry kernels.  The single-precision tiled build is compiled for three waves per SIMD (at most 168
+// registers): the build is bound by the latency of its dependent LDS and memory chains, which more resident
+// waves hide.  The persistent loop keeps the arguments' scalar loads live across its iterations; under the
+// same limit it spills, so it keeps the default.
+template <int G, bool LW>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) build_tiled_kernel(BuildP p) {
+  tiled_body<G, float, LW>(p);
+}
+
+template <int G, bool LW>
+__global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t n_tiles) {
+  persistent_body<G, float, LW>(p, n_tiles);
+}
+
+template <int G, bool LW>
+__global__ void __launch_bounds__(256) build_tiled_kernel_f64(BuildP p) {
+  tiled_body<G, double, LW>(p);
+}
+
+template <int G, bool LW>
+__global__ void __launch_bounds__(256) build_persistent_kernel_f64(BuildP p, int64_t n_tiles) {
+  persistent_body<G, double, LW>(p, n_tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -1010,10 +1128,18 @@ struct Launch {
 
 template <int G, typename T, bool LW>
 void launch_build(const Launch& c, const BuildP& p) {
-  if (c.persistent)
-    build_persistent_kernel<G, T, LW><<<c.grid, c.block, (c.block / 64) * sizeof(ScanLds<T>), c.stream>>>(p, c.n_tiles);
-  else
-    build_tiled_kernel<G, T, LW><<<c.grid, c.block, (c.block / 64) * sizeof(ScanLds<T>), c.stream>>>(p);
+  const size_t lds = (c.block / 64) * sizeof(ScanLds<T, LW>);
+  if constexpr (std::is_same<T, float>::value) {
+    if (c.persistent)
+      build_persistent_kernel<G, LW><<<c.grid, c.block, lds, c.stream>>>(p, c.n_tiles);
+    else
+      build_tiled_kernel<G, LW><<<c.grid, c.block, lds, c.stream>>>(p);
+  } else {
+    if (c.persistent)
+      build_persistent_kernel_f64<G, LW><<<c.grid, c.block, lds, c.stream>>>(p, c.n_tiles);
+    else
+      build_tiled_kernel_f64<G, LW><<<c.grid, c.block, lds, c.stream>>>(p);
+  }
 }
 
 template <int G>

@@ -36,7 +36,8 @@ def ctx():
     c.close()
 
 
-def _gpu_build(ctx, prob, N=6, mode=0, det32=None, counters=False, precision=1, mlp=None, nsigma=4.0):
+def _gpu_build(ctx, prob, N=6, mode=0, det32=None, counters=False, precision=1, mlp=None, nsigma=4.0,
+               chi2_cut=30.0):
     import torch
     from paper_1705_02876_amd import kfmi_build as KB, kfmi_mlp as M
     ctx.kf_set_geometry(det32)
@@ -46,7 +47,8 @@ def _gpu_build(ctx, prob, N=6, mode=0, det32=None, counters=False, precision=1, 
     if mlp is not None:
         packed = M.pack(ctx, torch.from_numpy(np.asarray(mlp, np.float32)).cuda(), M.new_packed())
     cfg = KB.make_cfg(max_cands=N, mode=mode, precision=precision,
-                      window_mode=KB.WINDOW_PLAIN if mlp is None else KB.WINDOW_LEARNED, learned_nsigma=nsigma)
+                      window_mode=KB.WINDOW_PLAIN if mlp is None else KB.WINDOW_LEARNED, learned_nsigma=nsigma,
+                      chi2_cut=chi2_cut)
     cnt = torch.zeros(KB.BUILD_COUNTERS, dtype=torch.int64, device="cuda") if counters else None
     out = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, counters=cnt, mlp_packed=packed)
     torch.cuda.synchronize()
@@ -267,6 +269,27 @@ def test_learned_window_limits_equal_plain(ctx, N, mode, precision):
             if k != "counters":
                 assert np.array_equal(plain[k], lw[k], equal_nan=True), (label, k)
         assert lw["counters"][5] == 0 if label == "huge" else lw["counters"][5] > 0
+
+
+@pytest.mark.parametrize("N,mode,precision", [(6, 1, 0), (2, 0, 1)])
+def test_learned_window_deferred_overflow(ctx, N, mode, precision):
+    """With a wide plain window (chi2 cut 2000) and a learned box that holds no hit, far more
+    box-passing pairs wait for the fallback than the deferred queue holds; the overflow is
+    evaluated at once, and the result is still the plain build exactly."""
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = S.make_build_problem([1500, 700], det, 68)
+    plain, _ = _gpu_build(ctx, prob, N=N, mode=mode, det32=det32, precision=precision, counters=True,
+                          chi2_cut=2000.0)
+    lw, _ = _gpu_build(ctx, prob, N=N, mode=mode, det32=det32, precision=precision, counters=True,
+                       mlp=_window_net([-40.0, -40.0], 0.0), chi2_cut=2000.0)
+    c = plain["counters"]
+    print(f"[learned overflow N={N}] plain counters {c}, learned {lw['counters']}", flush=True)
+    # box-passing pairs per candidate and layer far above what a wave's deferred queue holds per candidate
+    assert c[1] > 8 * c[3], c
+    for k in plain:
+        if k != "counters":
+            assert np.array_equal(plain[k], lw[k], equal_nan=True), k
 
 
 @pytest.mark.parametrize("N,mode,precision", [(6, 1, 1), (6, 0, 0), (1, 0, 1), (8, 1, 0)])
