@@ -112,14 +112,13 @@ __device__ __forceinline__ void load_hit(const float* __restrict__ hit_pos, cons
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const float* state_in,
-                                                  const float* cov_in, const int8_t* __restrict__ charge,
-                                                  const int32_t* __restrict__ hit_idx, int64_t ld_idx,
-                                                  const float* __restrict__ hit_pos,
-                                                  const float* __restrict__ hit_cov, int64_t ldh, float* state_out,
-                                                  float* cov_out, float* __restrict__ chi2_out,
-                                                  int32_t* __restrict__ nhits_out, int32_t* __restrict__ status_out,
-                                                  Geom g, float* __restrict__ res, int64_t ldr) {
+__device__ __forceinline__ void fit_body(int64_t n, int64_t ld, const float* state_in, const float* cov_in,
+                                         const int8_t* __restrict__ charge, const int32_t* __restrict__ hit_idx,
+                                         int64_t ld_idx, const float* __restrict__ hit_pos,
+                                         const float* __restrict__ hit_cov, int64_t ldh, float* state_out,
+                                         float* cov_out, float* __restrict__ chi2_out,
+                                         int32_t* __restrict__ nhits_out, int32_t* __restrict__ status_out,
+                                         const Geom& g, float* __restrict__ res, int64_t ldr) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int L = g.n_layers;
@@ -143,42 +142,47 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
   // Software pipeline over layers: the hit of layer l + 1 is fetched while
   // layer l is computed, and the hit index two layers ahead, so the dependent
   // gathers (index, then hit) overlap the arithmetic instead of stalling it.
+  // The state is updated in place.  A failing step stops the track; its last
+  // valid state is then recovered by replaying the track up to that step (rare:
+  // keeping a copy of the state at every step would cost every track).
   float m[3] = {0.f, 0.f, 0.f}, v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   int32_t h_cur = last >= 0 ? hit_idx[i] : -1;
   int32_t h_nxt = last >= 1 ? hit_idx[ld_idx + i] : -1;
   if (h_cur >= 0) load_hit(hit_pos, hit_cov, ldh, h_cur, m, v);
   float r_from = 0.f;
+  // layer and step that failed: 0 its crossing or its update (one step: the state before the layer is kept),
+  // 1 its material (the state after the update is kept)
+  int fail_l = 0, fail_step = 0;
   for (int l = 0; l <= last; ++l) {
     float mn[3] = {0.f, 0.f, 0.f}, vn[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const int32_t h_nn = (l + 2 <= last) ? hit_idx[static_cast<int64_t>(l + 2) * ld_idx + i] : -1;
     if (h_nxt >= 0) load_hit(hit_pos, hit_cov, ldh, h_nxt, mn, vn);
-    T s2[6], c2[21];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) s2[k] = s[k];
-#pragma unroll
-    for (int k = 0; k < 21; ++k) c2[k] = c[k];
-    st = propagate(s2, c2, a, T(g.r[l]), T(0));
-    if (st) break;
+    st = propagate(s, c, a, T(g.r[l]), T(0));
+    if (st) {
+      fail_l = l;
+      fail_step = 0;
+      break;
+    }
     if (h_cur >= 0) {
       T dc2;
-      if (res && l >= 1) emit_residual(res, ldr, i * (L - 1) + (l - 1), s2, c2, qf, r_from, g.r[l], g.z_half[l], m);
-      st = update_on_layer<T, double>(s2, c2, m, v, dc2);
-      if (st) break;
+      if (res && l >= 1) emit_residual(res, ldr, i * (L - 1) + (l - 1), s, c, qf, r_from, g.r[l], g.z_half[l], m);
+      st = update_on_layer<T, double>(s, c, m, v, dc2);
+      if (st) {
+        fail_l = l;
+        fail_step = 0;
+        break;
+      }
       chi2 += dc2;
       nh += 1;
     }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) s[k] = s2[k];
-#pragma unroll
-    for (int k = 0; k < 21; ++k) c[k] = c2[k];
     r_from = g.r[l];
     if (l < last) {
-      st = material(s2, c2, T(g.x_over_x0[l]), T(g.eloss_per_x0), T(g.mass));
-      if (st) break;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) s[k] = s2[k];
-#pragma unroll
-      for (int k = 0; k < 21; ++k) c[k] = c2[k];
+      st = material(s, c, T(g.x_over_x0[l]), T(g.eloss_per_x0), T(g.mass));
+      if (st) {
+        fail_l = l;
+        fail_step = 1;
+        break;
+      }
     }
     h_cur = h_nxt;
     h_nxt = h_nn;
@@ -187,11 +191,46 @@ __global__ void __launch_bounds__(256) fit_kernel(int64_t n, int64_t ld, const f
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[k] = vn[k];
   }
+  if (st) {
+    // replay the steps before the failing one (the same arithmetic in the same order: the same values)
+    load_track(state_in, cov_in, ld, i, s, c);
+    for (int l = 0; l <= fail_l; ++l) {
+      if (l == fail_l && fail_step == 0) break;
+      propagate(s, c, a, T(g.r[l]), T(0));
+      const int32_t h = hit_idx[static_cast<int64_t>(l) * ld_idx + i];
+      if (h >= 0) {
+        float mm[3], vv[6];
+        load_hit(hit_pos, hit_cov, ldh, h, mm, vv);
+        T dc2;
+        update_on_layer<T, double>(s, c, mm, vv, dc2);
+      }
+      if (l == fail_l) break;
+      material(s, c, T(g.x_over_x0[l]), T(g.eloss_per_x0), T(g.mass));
+    }
+  }
   store_track(state_out, cov_out, ld, i, s, c);
   chi2_out[i] = static_cast<float>(chi2);
   nhits_out[i] = nh;
   status_out[i] = st;
 }
+
+#define KF_FIT_PARAMS                                                                                             \
+  int64_t n, int64_t ld, const float *state_in, const float *cov_in, const int8_t *__restrict__ charge,          \
+      const int32_t *__restrict__ hit_idx, int64_t ld_idx, const float *__restrict__ hit_pos,                    \
+      const float *__restrict__ hit_cov, int64_t ldh, float *state_out, float *cov_out,                           \
+      float *__restrict__ chi2_out, int32_t *__restrict__ nhits_out, int32_t *__restrict__ status_out, Geom g,   \
+      float *__restrict__ res, int64_t ldr
+#define KF_FIT_ARGS                                                                                               \
+  n, ld, state_in, cov_in, charge, hit_idx, ld_idx, hit_pos, hit_cov, ldh, state_out, cov_out, chi2_out,         \
+      nhits_out, status_out, g, res, ldr
+
+// single precision: compiled for three waves per SIMD (at most 168 registers; the fit's dependent chains of
+// loads and arithmetic are latency bound); double precision keeps the default
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) fit_kernel(KF_FIT_PARAMS) {
+  fit_body<float>(KF_FIT_ARGS);
+}
+
+__global__ void __launch_bounds__(256) fit_kernel_f64(KF_FIT_PARAMS) { fit_body<double>(KF_FIT_ARGS); }
 
 }  // namespace
 
@@ -311,7 +350,7 @@ int32_t kf_fit(kf_ctx* ctx, const kf_fit_args* a) {
   if (!a->state_in || !a->cov_in || !a->charge || !a->hit_idx || !a->state_out || !a->cov_out || !a->chi2_out ||
       !a->nhits_out || !a->status_out)
     return set_error(KF_ERR_INVALID_ARG, "null array");
-  auto kern = (a->flags & KF_FIT_FP64) ? fit_kernel<double> : fit_kernel<float>;
+  auto kern = (a->flags & KF_FIT_FP64) ? fit_kernel_f64 : fit_kernel;
   kern<<<kfh::grid_for(a->n, 256), 256, 0, kfh::stream_of(a->stream)>>>(
       a->n, a->ld, a->state_in, a->cov_in, a->charge, a->hit_idx, a->ld_idx, a->hit_pos, a->hit_cov, a->ldh,
       a->state_out, a->cov_out, a->chi2_out, a->nhits_out, a->status_out, ctx->dgeom,

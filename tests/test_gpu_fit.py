@@ -101,6 +101,38 @@ def test_fit_edge_cases(ctx, orc):
                torch.empty(0, dtype=torch.int32, device="cuda"), torch.empty(0, dtype=torch.int32, device="cuda"))
 
 
+@pytest.mark.parametrize("fp64", [False, True])
+def test_fit_failing_tracks_keep_last_valid_state(ctx, orc, fp64):
+    """A track stops at its first failing step and reports the state before it: slow tracks given a hit on
+    the outermost layer, which they cannot reach, stop there with the state after the material of the layer
+    before; a 20 MeV track stops at the first layer and reports its input."""
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    fp = S.make_fit_problem(6000, det, 71, p_miss=0.05, min_hits=6)
+    L = det.n_layers
+    pt = np.hypot(fp.state0[:, 3], fp.state0[:, 4])
+    slow = np.nonzero((fp.hit_idx[L - 1] < 0) & (pt < 0.56))[0]
+    donor = int(np.nonzero(fp.hit_idx[L - 1] >= 0)[0][0])
+    fp.hit_idx[L - 1, slow] = fp.hit_idx[L - 1, donor]
+    first = int(np.nonzero(fp.hit_idx[L - 1] >= 0)[0][1])
+    fp.state0[first, 3:5] = [0.02, 0.0]
+    gs, gc, gchi, gnh, gst = _fit_gpu(ctx, fp, fp64=fp64)
+    os_, oc, ochi, onh, ost = oracle_fit_on_f32(orc, det32, fp)
+    stopped = slow[ost[slow] == 1]  # NO_CROSSING on the outermost layer
+    print(f"[fit failures] slow tracks {slow.size}, stopped at the last layer {stopped.size}", flush=True)
+    assert stopped.size >= 5
+    assert np.array_equal(gst[stopped], ost[stopped])
+    assert gst[first] == ost[first] == 1 and gnh[first] == 0 and gchi[first] == 0
+    assert np.array_equal(gs[first], rounded(fp.state0[first]))
+    sel = np.concatenate([stopped, [first]])
+    assert np.array_equal(gnh[sel], onh[sel])
+    check_params(gs[sel], os_[sel], "last valid state")
+    check_chi2(gchi[stopped], ochi[stopped], "chi2 up to the failure")
+    check_cov(gc[sel], oc[sel], "last valid covariance", rel=1e-2)
+    assert (gst == ost).mean() > 0.999
+
+
 def test_fit_rejects_bad_arguments(ctx):
     import torch
     from paper_1705_02876_amd import kfmi
