@@ -3,8 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "kf_internal.hpp"
 
@@ -16,22 +18,35 @@ thread_local std::string g_last_error = "no error";
 
 // Coalesced SoA loads/stores of one track's state and packed covariance
 // (float32 in HBM, T in registers).
-template <typename T>
-__device__ __forceinline__ void load_track(const float* __restrict__ st, const float* __restrict__ cv, int64_t ld,
-                                           int64_t i, T s[6], T c[21]) {
-#pragma unroll
-  for (int k = 0; k < 6; ++k) s[k] = T(__builtin_nontemporal_load(st + k * ld + i));
-#pragma unroll
-  for (int k = 0; k < 21; ++k) c[k] = T(__builtin_nontemporal_load(cv + k * ld + i));
+// Element idx of an array row whose start is uniform across the wave: with a 32-bit index the byte offset is
+// formed in 32 bits too (the caller keeps every array under 4 GiB), so an access is a scalar base plus a 32-bit
+// vector offset, without 64-bit address arithmetic per lane.
+template <typename P>
+__device__ __forceinline__ P* elem(P* base, uint32_t idx) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + idx * static_cast<uint32_t>(sizeof(P)));
+}
+template <typename P>
+__device__ __forceinline__ P* elem(P* base, int64_t idx) {
+  return base + idx;
 }
 
-template <typename T>
-__device__ __forceinline__ void store_track(float* __restrict__ st, float* __restrict__ cv, int64_t ld, int64_t i,
+template <typename T, typename I>
+__device__ __forceinline__ void load_track(const float* __restrict__ st, const float* __restrict__ cv, I ld, I i,
+                                           T s[6], T c[21]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[k] = T(__builtin_nontemporal_load(elem(st + k * static_cast<int64_t>(ld), i)));
+#pragma unroll
+  for (int k = 0; k < 21; ++k) c[k] = T(__builtin_nontemporal_load(elem(cv + k * static_cast<int64_t>(ld), i)));
+}
+
+template <typename T, typename I>
+__device__ __forceinline__ void store_track(float* __restrict__ st, float* __restrict__ cv, I ld, I i,
                                             const T s[6], const T c[21]) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(static_cast<float>(s[k]), st + k * ld + i);
+  for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(static_cast<float>(s[k]), elem(st + k * static_cast<int64_t>(ld), i));
 #pragma unroll
-  for (int k = 0; k < 21; ++k) __builtin_nontemporal_store(static_cast<float>(c[k]), cv + k * ld + i);
+  for (int k = 0; k < 21; ++k) __builtin_nontemporal_store(static_cast<float>(c[k]), elem(cv + k * static_cast<int64_t>(ld), i));
 }
 
 __global__ void __launch_bounds__(256) propagate_kernel(int64_t n, int64_t ld, float* state, float* cov,
@@ -88,8 +103,8 @@ __global__ void __launch_bounds__(256) update_kernel(int64_t n, int64_t ld, floa
 
 // Training record of a prediction for the learned search window: its
 // features, then the tangential and z offsets of the track's own hit.
-template <typename T>
-__device__ __forceinline__ void emit_residual(float* __restrict__ out, int64_t ldr, int64_t row, const T s[6],
+template <typename T, typename I>
+__device__ __forceinline__ void emit_residual(float* __restrict__ out, I ldr, I row, const T s[6],
                                               const T c[21], float q, float r_from, float r_to, float zh,
                                               const float m[3]) {
   float f[KF_RES_FEATURES];
@@ -98,37 +113,39 @@ __device__ __forceinline__ void emit_residual(float* __restrict__ out, int64_t l
   const float ir = __frsqrt_rn(x * x + y * y);
   const float tx = -y * ir, ty = x * ir;
 #pragma unroll
-  for (int k = 0; k < KF_RES_FEATURES; ++k) out[k * ldr + row] = f[k];
-  out[KF_RES_FEATURES * ldr + row] = tx * (m[0] - x) + ty * (m[1] - y);
-  out[(KF_RES_FEATURES + 1) * ldr + row] = m[2] - z;
+  for (int k = 0; k < KF_RES_FEATURES; ++k) *elem(out + k * static_cast<int64_t>(ldr), row) = f[k];
+  *elem(out + KF_RES_FEATURES * static_cast<int64_t>(ldr), row) = tx * (m[0] - x) + ty * (m[1] - y);
+  *elem(out + (KF_RES_FEATURES + 1) * static_cast<int64_t>(ldr), row) = m[2] - z;
 }
 
-__device__ __forceinline__ void load_hit(const float* __restrict__ hit_pos, const float* __restrict__ hit_cov,
-                                         int64_t ldh, int32_t h, float m[3], float v[6]) {
+template <typename I>
+__device__ __forceinline__ void load_hit(const float* __restrict__ hit_pos, const float* __restrict__ hit_cov, I ldh,
+                                         int32_t h, float m[3], float v[6]) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) m[k] = hit_pos[k * ldh + h];
+  for (int k = 0; k < 3; ++k) m[k] = *elem(hit_pos + k * static_cast<int64_t>(ldh), static_cast<I>(h));
 #pragma unroll
-  for (int k = 0; k < 6; ++k) v[k] = hit_cov[k * ldh + h];
+  for (int k = 0; k < 6; ++k) v[k] = *elem(hit_cov + k * static_cast<int64_t>(ldh), static_cast<I>(h));
 }
 
-template <typename T>
-__device__ __forceinline__ void fit_body(int64_t n, int64_t ld, const float* state_in, const float* cov_in,
+template <typename T, typename I>
+__device__ __forceinline__ void fit_body(I n, I ld, const float* state_in, const float* cov_in,
                                          const int8_t* __restrict__ charge, const int32_t* __restrict__ hit_idx,
-                                         int64_t ld_idx, const float* __restrict__ hit_pos,
-                                         const float* __restrict__ hit_cov, int64_t ldh, float* state_out,
+                                         I ld_idx, const float* __restrict__ hit_pos,
+                                         const float* __restrict__ hit_cov, I ldh, float* state_out,
                                          float* cov_out, float* __restrict__ chi2_out,
                                          int32_t* __restrict__ nhits_out, int32_t* __restrict__ status_out,
-                                         const Geom& g, float* __restrict__ res, int64_t ldr) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+                                         const Geom& g, float* __restrict__ res, I ldr) {
+  const I i = static_cast<I>(blockIdx.x) * static_cast<I>(blockDim.x) + static_cast<I>(threadIdx.x);
   if (i >= n) return;
   const int L = g.n_layers;
   T s[6], c[21];
   load_track(state_in, cov_in, ld, i, s, c);
-  const float qf = static_cast<float>(charge[i]);
-  const T a = T(-static_cast<double>(charge[i]) * kCLight * g.bz);
+  const int8_t qi = *elem(charge, i);
+  const float qf = static_cast<float>(qi);
+  const T a = T(-static_cast<double>(qi) * kCLight * g.bz);
   int last = -1;  // last layer with a hit: searched from the outside in (most tracks end near the outer layers)
   for (int l = L - 1; l >= 0; --l)
-    if (hit_idx[l * ld_idx + i] >= 0) {
+    if (*elem(hit_idx + l * static_cast<int64_t>(ld_idx), i) >= 0) {
       last = l;
       break;
     }
@@ -137,7 +154,7 @@ __device__ __forceinline__ void fit_body(int64_t n, int64_t ld, const float* sta
   if (res) {
     for (int l = 1; l < L; ++l)
 #pragma unroll
-      for (int k = 0; k < KF_RES_FEATURES + 2; ++k) res[k * ldr + i * (L - 1) + (l - 1)] = NAN;
+      for (int k = 0; k < KF_RES_FEATURES + 2; ++k) *elem(res + k * static_cast<int64_t>(ldr), i * static_cast<I>(L - 1) + static_cast<I>(l - 1)) = NAN;
   }
   // Software pipeline over layers: the hit of layer l + 1 is fetched while
   // layer l is computed, and the hit index two layers ahead, so the dependent
@@ -146,8 +163,8 @@ __device__ __forceinline__ void fit_body(int64_t n, int64_t ld, const float* sta
   // valid state is then recovered by replaying the track up to that step (rare:
   // keeping a copy of the state at every step would cost every track).
   float m[3] = {0.f, 0.f, 0.f}, v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int32_t h_cur = last >= 0 ? hit_idx[i] : -1;
-  int32_t h_nxt = last >= 1 ? hit_idx[ld_idx + i] : -1;
+  int32_t h_cur = last >= 0 ? *elem(hit_idx, i) : -1;
+  int32_t h_nxt = last >= 1 ? *elem(hit_idx + static_cast<int64_t>(ld_idx), i) : -1;
   if (h_cur >= 0) load_hit(hit_pos, hit_cov, ldh, h_cur, m, v);
   float r_from = 0.f;
   // layer and step that failed: 0 its crossing or its update (one step: the state before the layer is kept),
@@ -155,7 +172,7 @@ __device__ __forceinline__ void fit_body(int64_t n, int64_t ld, const float* sta
   int fail_l = 0, fail_step = 0;
   for (int l = 0; l <= last; ++l) {
     float mn[3] = {0.f, 0.f, 0.f}, vn[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const int32_t h_nn = (l + 2 <= last) ? hit_idx[static_cast<int64_t>(l + 2) * ld_idx + i] : -1;
+    const int32_t h_nn = (l + 2 <= last) ? *elem(hit_idx + (l + 2) * static_cast<int64_t>(ld_idx), i) : -1;
     if (h_nxt >= 0) load_hit(hit_pos, hit_cov, ldh, h_nxt, mn, vn);
     st = propagate(s, c, a, T(g.r[l]), T(0));
     if (st) {
@@ -165,7 +182,7 @@ __device__ __forceinline__ void fit_body(int64_t n, int64_t ld, const float* sta
     }
     if (h_cur >= 0) {
       T dc2;
-      if (res && l >= 1) emit_residual(res, ldr, i * (L - 1) + (l - 1), s, c, qf, r_from, g.r[l], g.z_half[l], m);
+      if (res && l >= 1) emit_residual(res, ldr, i * static_cast<I>(L - 1) + static_cast<I>(l - 1), s, c, qf, r_from, g.r[l], g.z_half[l], m);
       st = update_on_layer<T, double>(s, c, m, v, dc2);
       if (st) {
         fail_l = l;
@@ -197,7 +214,7 @@ __device__ __forceinline__ void fit_body(int64_t n, int64_t ld, const float* sta
     for (int l = 0; l <= fail_l; ++l) {
       if (l == fail_l && fail_step == 0) break;
       propagate(s, c, a, T(g.r[l]), T(0));
-      const int32_t h = hit_idx[static_cast<int64_t>(l) * ld_idx + i];
+      const int32_t h = *elem(hit_idx + l * static_cast<int64_t>(ld_idx), i);
       if (h >= 0) {
         float mm[3], vv[6];
         load_hit(hit_pos, hit_cov, ldh, h, mm, vv);
@@ -209,9 +226,9 @@ __device__ __forceinline__ void fit_body(int64_t n, int64_t ld, const float* sta
     }
   }
   store_track(state_out, cov_out, ld, i, s, c);
-  chi2_out[i] = static_cast<float>(chi2);
-  nhits_out[i] = nh;
-  status_out[i] = st;
+  *elem(chi2_out, i) = static_cast<float>(chi2);
+  *elem(nhits_out, i) = nh;
+  *elem(status_out, i) = st;
 }
 
 #define KF_FIT_PARAMS                                                                                             \
@@ -223,14 +240,24 @@ __device__ __forceinline__ void fit_body(int64_t n, int64_t ld, const float* sta
 #define KF_FIT_ARGS                                                                                               \
   n, ld, state_in, cov_in, charge, hit_idx, ld_idx, hit_pos, hit_cov, ldh, state_out, cov_out, chi2_out,         \
       nhits_out, status_out, g, res, ldr
+#define KF_FIT_ARGS32                                                                                             \
+  static_cast<uint32_t>(n), static_cast<uint32_t>(ld), state_in, cov_in, charge, hit_idx,                         \
+      static_cast<uint32_t>(ld_idx), hit_pos, hit_cov, static_cast<uint32_t>(ldh), state_out, cov_out, chi2_out, \
+      nhits_out, status_out, g, res, static_cast<uint32_t>(ldr)
 
 // single precision: compiled for three waves per SIMD (at most 168 registers; the fit's dependent chains of
 // loads and arithmetic are latency bound); double precision keeps the default
+// With every array under 4 GiB the element offsets are computed in 32 bits, so the loads address a scalar base
+// plus a 32-bit offset instead of doing 64-bit address arithmetic per access.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) fit_kernel(KF_FIT_PARAMS) {
-  fit_body<float>(KF_FIT_ARGS);
+  fit_body<float, uint32_t>(KF_FIT_ARGS32);
 }
 
-__global__ void __launch_bounds__(256) fit_kernel_f64(KF_FIT_PARAMS) { fit_body<double>(KF_FIT_ARGS); }
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) fit_kernel_i64(KF_FIT_PARAMS) {
+  fit_body<float, int64_t>(KF_FIT_ARGS);
+}
+
+__global__ void __launch_bounds__(256) fit_kernel_f64(KF_FIT_PARAMS) { fit_body<double, int64_t>(KF_FIT_ARGS); }
 
 }  // namespace
 
@@ -350,7 +377,11 @@ int32_t kf_fit(kf_ctx* ctx, const kf_fit_args* a) {
   if (!a->state_in || !a->cov_in || !a->charge || !a->hit_idx || !a->state_out || !a->cov_out || !a->chi2_out ||
       !a->nhits_out || !a->status_out)
     return set_error(KF_ERR_INVALID_ARG, "null array");
-  auto kern = (a->flags & KF_FIT_FP64) ? fit_kernel_f64 : fit_kernel;
+  // 32-bit element offsets when every array's byte extent stays below 4 GiB
+  const int64_t ext = std::max({21 * a->ld, static_cast<int64_t>(L) * a->ld_idx, 6 * a->ldh,
+                                emit ? (KF_RES_FEATURES + 2) * a->ld_res : int64_t(0)});
+  const bool narrow = ext < (int64_t(1) << 30);
+  auto kern = (a->flags & KF_FIT_FP64) ? fit_kernel_f64 : (narrow ? fit_kernel : fit_kernel_i64);
   kern<<<kfh::grid_for(a->n, 256), 256, 0, kfh::stream_of(a->stream)>>>(
       a->n, a->ld, a->state_in, a->cov_in, a->charge, a->hit_idx, a->ld_idx, a->hit_pos, a->hit_cov, a->ldh,
       a->state_out, a->cov_out, a->chi2_out, a->nhits_out, a->status_out, ctx->dgeom,
