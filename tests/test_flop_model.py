@@ -24,6 +24,9 @@ def _host_header(dst):
     src = src.replace("__builtin_amdgcn_rsqf(x)", "1.0f / std::sqrt(x)")
     src = src.replace("__builtin_amdgcn_sqrtf(x)", "std::sqrt(x)")
     src = src.replace("a * __builtin_amdgcn_rcpf(b)", "a / b")
+    src = src.replace("__builtin_amdgcn_rcpf(x)", "1.0f / x")
+    src = src.replace("__builtin_amdgcn_rcp(x)", "1.0 / x")
+    src = src.replace("__builtin_amdgcn_rsq(x)", "1.0 / std::sqrt(x)")
     src = src.replace("__device__ __forceinline__", "static inline")
     src = src.replace("KF_DEV double copysign_t(double a, double b) { return copysign(a, b); }",
                       "KF_DEV double copysign_t(double a, double b) { return copysign(a, b); }\n"
@@ -33,7 +36,9 @@ def _host_header(dst):
                       "KF_DEV CF sqrt_t(CF x) { cnt_sqrt++; return CF::raw(std::sqrt(x.v)); }\n"
                       "KF_DEV CF abs_t(CF x) { return CF::raw(std::fabs(x.v)); }\n"
                       "KF_DEV CF copysign_t(CF a, CF b) { return CF::raw(std::copysign(a.v, b.v)); }\n"
-                      "KF_DEV CF div_t(CF a, CF b) { return a / b; }")
+                      "KF_DEV CF div_t(CF a, CF b) { return a / b; }\n"
+                      "KF_DEV CF rcp_pos(CF x) { return CF(1) / x; }\n"
+                      "KF_DEV CF rsqrt_pos(CF x) { return CF(1) / sqrt(x); }")
     open(dst, "w").write(src)
 
 
