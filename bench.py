@@ -49,6 +49,7 @@ def fit_bytes(n, L, n_hits_total):
 KERNEL_SOURCES = {
     "fit_kernel": ("kf_fit.hip", "kf_device.hpp", "kf_internal.hpp"),
     "bin_kernel": ("kf_build.hip", "kf_device.hpp", "kf_internal.hpp"),
+    "bin_fine_kernel": ("kf_build.hip", "kf_device.hpp", "kf_internal.hpp"),
     "build_persistent_kernel": ("kf_build.hip", "kf_device.hpp", "kf_mlp_device.hpp", "kf_internal.hpp"),
     "build_tiled_kernel": ("kf_build.hip", "kf_device.hpp", "kf_mlp_device.hpp", "kf_internal.hpp"),
 }
@@ -61,6 +62,8 @@ def source_digest(kernel):
     for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1705_02876_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1705_02876_amd", "build_lib.py"), "rb") as fh:  # compiler flags
+        h.update(fh.read())
     return h.hexdigest()
 
 
@@ -214,8 +217,10 @@ def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, pl
     t1.record(stream)
     torch.cuda.synchronize()
     train_ms = t0.elapsed_time(t1)
+    # without the autotuner: four waves per block share the network weights staged in each block's LDS
+    lwpb = args.learned_wpb if args.learned_wpb > 0 else (cfg.waves_per_block if args.build_mode == "auto" else 4)
     lcfg = KB.make_cfg(max_cands=N, mode=cfg.mode, precision=cfg.precision, window_mode=KB.WINDOW_LEARNED,
-                       learned_nsigma=args.nsigma, waves_per_block=cfg.waves_per_block,
+                       learned_nsigma=args.nsigma, waves_per_block=lwpb,
                        blocks_per_cu=cfg.blocks_per_cu, n_phi=cfg.n_phi, n_eta=cfg.n_eta)
     lws = torch.empty(KB.workspace_bytes(lcfg, bp.n_events, seeds["n"]), dtype=torch.uint8, device="cuda")
     lout = KB.build(ctx, lcfg, seeds, bins, hits["layer_offsets"], bp.n_events, mlp_packed=tr.packed, workspace=lws)
@@ -269,6 +274,8 @@ def main():
                          "the candidates do not depend on the grid")
     ap.add_argument("--build-wpb", type=int, default=0, help="waves per block when --build-mode is not auto")
     ap.add_argument("--build-bpc", type=int, default=0, help="persistent blocks per CU when --build-mode is not auto")
+    ap.add_argument("--learned-wpb", type=int, default=0,
+                    help="waves per block of the learned-window build when --build-mode is not auto (default 4)")
     ap.add_argument("--fit-fp64", action="store_true", help="double-precision registers in the fit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-window leg")
     ap.add_argument("--nsigma", type=float, default=2.5, help="learned window half width in network scales")
@@ -404,7 +411,9 @@ def main():
     fb = fit_bytes(n, L, n_hits)
     ff = fit_flops(fp)
     kern["fit_kernel"] = dict(avg_ms=fit_ms, flop=ff, bytes=fb)
-    kern["bin_kernel"] = dict(avg_ms=bin_ms, flop=0, bytes=bin_bytes(bp, L))
+    # one binning kernel per launch: per-wave histograms up to 2048 bins, one histogram per block above
+    kern["bin_kernel" if n_phi * n_eta <= 2048 else "bin_fine_kernel"] = dict(avg_ms=bin_ms, flop=0,
+                                                                              bytes=bin_bytes(bp, L))
     kern["build_persistent_kernel" if cfg.mode == KB.BUILD_PERSISTENT else "build_tiled_kernel"] = dict(
         avg_ms=build_ms, flop=build_flops(counters), bytes=build_bytes(bp, N, L))
     for k, v in kern.items():

@@ -287,8 +287,13 @@ __global__ void __launch_bounds__(kBinThreads) bin_fine_kernel(int32_t L, const 
     }
   }
   __syncthreads();
-  for (int64_t slot = lo + tid; slot < hi; slot += kBinThreads) {
-    const int64_t h = perm[slot];
+  // Records: the inverse permutation (into the bin-number array, no longer needed) lets the hits be read in index
+  // order, coalesced, and each record be written to its slot.  Gathering the hits in slot order instead reads a
+  // scattered word per access from hit arrays that, over all blocks of a die, do not fit in its L2.
+  for (int64_t slot = lo + tid; slot < hi; slot += kBinThreads) bins[perm[slot]] = static_cast<int32_t>(slot - lo);
+  __syncthreads();
+  for (int64_t h = lo + tid; h < hi; h += kBinThreads) {
+    const int64_t slot = lo + bins[h];
     float4* rec = reinterpret_cast<float4*>(binned + slot * KF_BINNED_FLOATS);
     rec[0] = make_float4(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h],
                          __int_as_float(static_cast<int32_t>(h - lo)));
@@ -450,7 +455,9 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
   T chi2 = T(0);
   int nhits = 3;
   int nc = seed_ok ? 1 : 0;  // candidates of this seed (same in all its lanes)
-  uint32_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0, n_fb = 0;  // per lane and tile
+  // work counters of the wave and tile: kept wave-uniform (counted with ballots at converged points) so that they
+  // occupy scalar registers rather than six vector registers for the whole tile
+  uint32_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0, n_fb = 0;
   const float qf = seed_ok ? static_cast<float>(p.seed_charge[s]) : 1.f;
   // one ScanLds per wave of the block, in dynamic LDS sized by the launch (blockDim / 64 of them)
   extern __shared__ __align__(16) unsigned char build_lds[];
@@ -468,6 +475,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
 #pragma unroll
     for (int k = 0; k < 21; ++k) pc[k] = cv[k];
     int32_t pstat = status;
+    n_steps += __popcll(__ballot(active && status == 0));
     if (active && status == 0) {
       int32_t r = material(ps, pc, T(p.g.x_over_x0[l - 1]), T(p.g.eloss_per_x0), T(p.g.mass));
       if (!r) r = propagate(ps, pc, a, T(p.g.r[l]), T(p.g.z_half[l]));
@@ -478,7 +486,6 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
 #pragma unroll
         for (int k = 0; k < 21; ++k) pc[k] = cv[k];
       }
-      n_steps++;
     }
     // ---- scan the window's bins, keep the best N children of this candidate
     T lkey[G];
@@ -618,13 +625,13 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
             L.att = C.pred[5][oq];
             L.atz = C.pred[6][oq];
             L.azz = C.pred[7][oq];
-            n_chi2++;
             if (!chi2_on_layer(pos3, L, mm, vv, c2) && c2 < T(p.chi2_cut)) {
               comp = true;
-              n_comp++;
               hidx = __float_as_int(h.w) | (LW ? ((qo >> 6) << 30) : 0);
             }
           }
+          n_chi2 += nb;
+          n_comp += __popcll(__ballot(comp));
           // group the compatible results by candidate: per-candidate counts, their prefix, then each
           // result at its candidate's start plus its rank (the insertion order does not matter: the
           // top-N list orders by its key)
@@ -748,6 +755,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
         C.off[lane] = incl - mine;
         wave_lds_sync();
         for (int base = 0; base < total; base += 64 * kScanUnroll) {
+          n_box += min(total - base, 64 * kScanUnroll);
           int own[kScanUnroll], js[kScanUnroll];
           float4 hv[kScanUnroll];
 #pragma unroll
@@ -772,7 +780,6 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
             const int w = base + 64 * u + lane;
             bool in_box = false, out_box = false;
             if (w < total) {
-              n_box++;
               const int o = own[u];
               // tangent (-ny, nx) at the prediction
               const float dx = hv[u].x - float(C.pred[0][o]), dy = hv[u].y - float(C.pred[1][o]);
@@ -822,7 +829,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       flush(true);
       if (LW) {
         const bool need = tighter && cnt_in == 0;
-        if (need) n_fb++;
+        n_fb += __popcll(__ballot(need));
         if (qb > 0) {
           // the rest of the fallbacks: candidates whose pairs inside the learned box all failed the cut
           wave_lds_sync();
@@ -888,6 +895,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
 #pragma unroll
     for (int k = 0; k < 21; ++k) cv[k] = __shfl(pc[k], src);
     status = __shfl(pstat, src);
+    n_upd += __popcll(__ballot(mine != ~0ull && key_hit(mine) != kHole && status == 0));
     if (mine != ~0ull) {
       nhits = key_nhits(mine);
       chi2 = mine_chi2;
@@ -901,7 +909,6 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
         T dc2;
         const int32_t r = update_on_layer<T, double>(st, cv, m, v, dc2);
         if (r) status = r;
-        n_upd++;
       }
       p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + slot] =
           static_cast<int32_t>((static_cast<uint32_t>(key_parent(mine)) << 24) | hid);
@@ -947,15 +954,11 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + slot] = out;
     }
   }
-  if (p.counters) {
-    uint64_t v[KF_BUILD_COUNTERS] = {n_box, n_chi2, n_comp, n_steps, n_upd, n_fb};
+  if (p.counters && lane == 0) {
+    const uint32_t v[KF_BUILD_COUNTERS] = {n_box, n_chi2, n_comp, n_steps, n_upd, n_fb};
 #pragma unroll
-    for (int i = 0; i < KF_BUILD_COUNTERS; ++i) {
-      uint64_t x = v[i];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-      if (lane == 0 && x) atomicAdd(&p.counters[i], static_cast<unsigned long long>(x));
-    }
+    for (int i = 0; i < KF_BUILD_COUNTERS; ++i)
+      if (v[i]) atomicAdd(&p.counters[i], static_cast<unsigned long long>(v[i]));
   }
 }
 
