@@ -347,14 +347,28 @@ __device__ __forceinline__ float key_chi2(uint64_t k) {
 __device__ __forceinline__ int key_parent(uint64_t k) { return static_cast<int>((k >> 24) & 7u); }
 __device__ __forceinline__ uint32_t key_hit(uint64_t k) { return static_cast<uint32_t>(k & kHole); }
 
+// minimum of k over the G lanes of this lane's seed group (groups of G consecutive lanes)
 template <int G>
 __device__ __forceinline__ uint64_t group_min(uint64_t k) {
+  if constexpr ((G & (G - 1)) == 0) {
 #pragma unroll
-  for (int off = 1; off < G; off <<= 1) {
-    const uint64_t o = __shfl_xor(k, off);
-    k = o < k ? o : k;
+    for (int off = 1; off < G; off <<= 1) {
+      const uint64_t o = __shfl_xor(k, off);
+      k = o < k ? o : k;
+    }
+    return k;
+  } else {
+    // rotations by 1, 2, 4 within the group cover it (G <= 8); lanes past the last whole group get no minimum
+    const int lane = threadIdx.x & 63;
+    const int slot = lane % G, base = lane - slot;
+#pragma unroll
+    for (int r = 1; r < G; r <<= 1) {
+      const int from = base + (slot + r < G ? slot + r : slot + r - G);
+      const uint64_t o = __shfl(k, from);
+      k = o < k ? o : k;
+    }
+    return lane < (64 / G) * G ? k : ~0ull;
   }
-  return k;
 }
 
 __device__ __forceinline__ int phi_bin_f(float phi, int n_phi) {
@@ -418,12 +432,12 @@ __device__ __forceinline__ int wave_max_i(int v) {
 
 template <int G, typename T, bool LW>
 __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* mlp_lds) {
-  constexpr int SPW = 64 / G;  // seeds per wave
+  constexpr int SPW = 64 / G;  // seeds per wave (G = 6: ten seeds, lanes 60..63 hold none)
   const int lane = threadIdx.x & 63;
   const int slot = lane % G;
   const int gbase = lane - slot;
   const int64_t pos = tile * SPW + lane / G;
-  const bool seed_ok = pos < p.n_seeds;
+  const bool seed_ok = lane < SPW * G && pos < p.n_seeds;
   const int64_t s = (seed_ok && p.order) ? static_cast<int64_t>(p.order[pos]) : pos;
   const int L = p.g.n_layers;
   const int N = p.max_cands;
@@ -1120,7 +1134,8 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
-int lanes_for(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8; }
+// lanes per seed: the candidates of a seed sit in G consecutive lanes (G = 6 keeps 60 of 64 lanes busy for N = 5, 6)
+int lanes_for(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : n <= 6 ? 6 : 8; }
 
 struct Launch {
   bool persistent, f64, learned;
@@ -1159,6 +1174,7 @@ void launch_any(int G, const Launch& c, const BuildP& p) {
     case 1: launch_g<1>(c, p); break;
     case 2: launch_g<2>(c, p); break;
     case 4: launch_g<4>(c, p); break;
+    case 6: launch_g<6>(c, p); break;
     default: launch_g<8>(c, p); break;
   }
 }
