@@ -71,6 +71,18 @@ __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// One K = 32 product (v_mfma_f32_16x16x32_bf16) standing for two K = 16 products over consecutive K tiles:
+// each operand is its two K = 16 lane fragments side by side.  A given (lane group, element) slot then holds the
+// same K index in both operands, so the sum is over the same 32 indices, in the hardware's accumulation order.
+__device__ __forceinline__ f32x4 mfma32(bf16x4 a0, bf16x4 a1, bf16x4 b0, bf16x4 b1, f32x4 c) {
+  typedef short s16x8 __attribute__((ext_vector_type(8)));
+  typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+  const s16x8 a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+  const s16x8 b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
 __device__ __forceinline__ bf16x4 load_tile(const unsigned char* packed, int off, int t, int lane) {
   return reinterpret_cast<const bf16x4*>(packed + off + t * kTileBytes)[lane];
 }
@@ -187,7 +199,8 @@ __device__ __forceinline__ void stage_forward(const unsigned char* __restrict__ 
 // lanes that hold a record: `src` maps compacted record k < n to its lane (a
 // per-wave LDS table), `pos` is this lane's compacted index (or -1).  Tiles
 // past n records are skipped, so a wave with few live candidates pays for few
-// products.
+// products.  The 64-wide layers use K = 32 products (14 per record tile
+// instead of 24).
 __device__ __forceinline__ void eval_compact_lds(const unsigned char* lds, const float f[kIn], int lane,
                                                  const int32_t* src_lane, int n, int pos, float& o0, float& o1) {
   const int g = lane >> 4, q = 4 * g;
@@ -226,14 +239,17 @@ __device__ __forceinline__ void eval_compact_lds(const unsigned char* lds, const
     for (int mt = 0; mt < 4; ++mt) {
       f32x4 a = z;
 #pragma unroll
-      for (int kt = 0; kt < 4; ++kt) a = mfma(load_tile(wl, kPkW2, mt * 4 + kt, lane), h1b[kt], a);
+      for (int kt = 0; kt < 4; kt += 2)
+        a = mfma32(load_tile(wl, kPkW2, mt * 4 + kt, lane), load_tile(wl, kPkW2, mt * 4 + kt + 1, lane), h1b[kt],
+                   h1b[kt + 1], a);
 #pragma unroll
       for (int e = 0; e < 4; ++e) a[e] = fmaxf(a[e] + b2[16 * mt + q + e], 0.f);
       h2b[mt] = to_bf16x4(a);
     }
     f32x4 o = z;
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt) o = mfma(load_tile(wl, kPkW3, kt, lane), h2b[kt], o);
+    for (int kt = 0; kt < 4; kt += 2)
+      o = mfma32(load_tile(wl, kPkW3, kt, lane), load_tile(wl, kPkW3, kt + 1, lane), h2b[kt], h2b[kt + 1], o);
     // record 16 t + j's outputs sit in lane j; its owner has compacted index 16 t + j
     const int from = pos >= 0 ? (pos & 15) : 0;
     const float r0 = __shfl(o[0] + b3[0], from);
