@@ -156,24 +156,24 @@ __device__ __forceinline__ void fit_body(I n, I ld, const float* state_in, const
 #pragma unroll
       for (int k = 0; k < KF_RES_FEATURES + 2; ++k) *elem(res + k * static_cast<int64_t>(ldr), i * static_cast<I>(L - 1) + static_cast<I>(l - 1)) = NAN;
   }
-  // Software pipeline over layers: the hit of layer l + 1 is fetched while
-  // layer l is computed, and the hit index two layers ahead, so the dependent
-  // gathers (index, then hit) overlap the arithmetic instead of stalling it.
+  // The hit of layer l is fetched at the start of its iteration, before the
+  // crossing, whose arithmetic covers the gather's latency; its index is read
+  // one layer ahead.  A layer without a hit loads hit 0 instead (never used;
+  // the track has a hit, so the arrays are not empty), so the loads need no
+  // branch and no zeroed registers.
   // The state is updated in place.  A failing step stops the track; its last
   // valid state is then recovered by replaying the track up to that step (rare:
   // keeping a copy of the state at every step would cost every track).
-  float m[3] = {0.f, 0.f, 0.f}, v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int32_t h_cur = last >= 0 ? *elem(hit_idx, i) : -1;
-  int32_t h_nxt = last >= 1 ? *elem(hit_idx + static_cast<int64_t>(ld_idx), i) : -1;
-  if (h_cur >= 0) load_hit(hit_pos, hit_cov, ldh, h_cur, m, v);
+  int32_t h_nxt = last >= 0 ? *elem(hit_idx, i) : -1;
   float r_from = 0.f;
   // layer and step that failed: 0 its crossing or its update (one step: the state before the layer is kept),
   // 1 its material (the state after the update is kept)
   int fail_l = 0, fail_step = 0;
   for (int l = 0; l <= last; ++l) {
-    float mn[3] = {0.f, 0.f, 0.f}, vn[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const int32_t h_nn = (l + 2 <= last) ? *elem(hit_idx + (l + 2) * static_cast<int64_t>(ld_idx), i) : -1;
-    if (h_nxt >= 0) load_hit(hit_pos, hit_cov, ldh, h_nxt, mn, vn);
+    const int32_t h_cur = h_nxt;
+    float m[3], v[6];
+    load_hit(hit_pos, hit_cov, ldh, h_cur >= 0 ? h_cur : 0, m, v);
+    h_nxt = (l + 1 <= last) ? *elem(hit_idx + (l + 1) * static_cast<int64_t>(ld_idx), i) : -1;
     st = propagate(s, c, a, T(g.r[l]), T(0));
     if (st) {
       fail_l = l;
@@ -201,12 +201,6 @@ __device__ __forceinline__ void fit_body(I n, I ld, const float* state_in, const
         break;
       }
     }
-    h_cur = h_nxt;
-    h_nxt = h_nn;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) m[k] = mn[k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = vn[k];
   }
   if (st) {
     // replay the steps before the failing one (the same arithmetic in the same order: the same values)
