@@ -74,6 +74,12 @@ def _declare(L):
     L.or_fit.restype = C.c_int32
     L.or_fit.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, P, P, P, P]
     L.or_bin_hits.restype = C.c_int32
+    L.or_smooth.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, P, P]
+    L.or_smooth.restype = C.c_int32
+    L.or_surface_pinv.argtypes = [P, C.c_double, C.c_double, P]
+    L.or_surface_pinv.restype = C.c_int32
+    L.or_rts_step.argtypes = [P] * 10
+    L.or_rts_step.restype = None
     L.or_bin_hits.argtypes = [P, C.c_int64, P, P, C.c_int32, C.c_int32, P, P, P]
     L.or_build.restype = C.c_int32
     L.or_build.argtypes = [P, P, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, C.c_int32] + [P] * 12
@@ -187,6 +193,41 @@ def fit(g, state0, cov0, q, hit_idx_LN, hit_pos, hit_cov_full):
                       _p(chi2), _p(nh), _p(st))
     assert rc == 0
     return so, co, chi2, nh, st
+
+
+def smooth(g, state0, cov0, q, hit_idx_LN, hit_pos, hit_cov_full):
+    """Smoothed state (n, L, 6) and covariance (n, L, 6, 6) at every layer up to
+    the last hit layer (NaN after it), and the fit status (n,)."""
+    state0 = _f64(state0)
+    n = state0.shape[0]
+    cov0 = _f64(cov0, (n, 6, 6))
+    L = g.n_layers
+    q8 = np.ascontiguousarray(q, dtype=np.int8)
+    hidx = np.ascontiguousarray(np.asarray(hit_idx_LN, dtype=np.int32).T)
+    hp = _f64(hit_pos)
+    hc = _f64(hit_cov_full)
+    so = np.zeros((n, L, 6))
+    co = np.zeros((n, L, 6, 6))
+    st = np.zeros(n, dtype=np.int32)
+    rc = lib().or_smooth(C.byref(g), n, _p(state0), _p(cov0), _p(q8), _p(hidx), _p(hp), _p(hc), _p(so), _p(co),
+                         _p(st))
+    assert rc == 0
+    return so, co, st
+
+
+def surface_pinv(Cm, x, y):
+    Cm = _f64(Cm, (6, 6))
+    out = np.zeros((6, 6))
+    ok = lib().or_surface_pinv(_p(Cm), float(x), float(y), _p(out))
+    return out if ok else None
+
+
+def rts_step(xf, Cf, F, xp, Cp, Cp_inv, xs_next, Cs_next):
+    a = [_f64(v) for v in (xf, Cf, F, xp, Cp, Cp_inv, xs_next, Cs_next)]
+    xs = np.zeros(6)
+    Cs = np.zeros((6, 6))
+    lib().or_rts_step(*[_p(v) for v in a], _p(xs), _p(Cs))
+    return xs, Cs
 
 
 def bin_hits(g, n_events, layer_offsets, hit_pos, n_phi=64, n_eta=16):

@@ -393,6 +393,59 @@ int32_t or_update(int64_t n, double* state, double* cov, const double* hit_pos, 
 /* Fit: start from the given prior at the vertex and, layer by layer up to the
  * last layer carrying a hit, propagate, update with the hit if there is one,
  * and add the layer's material unless it is the last hit layer. */
+/* Kalman filter of one track over its assigned hits, inside out (layers
+ * 0 .. last hit layer).  On success s, C hold the state after the last update.
+ * A failed crossing or update keeps the state from before that layer; a failed
+ * material step keeps the state after that layer's update.  rows_s [L][6] and
+ * rows_C [L][36] (nullable) receive the filtered state of every layer the
+ * filter completed (after its update, or the prediction on a layer without a
+ * hit, before its material); *done the number of such layers. */
+static int32_t fit_track(const or_geometry* g, double* s, double* C, int32_t q, const int32_t* hi,
+                         const double* hit_pos, const double* hit_cov, double* chi2_out, int32_t* nhits_out,
+                         double* rows_s, double* rows_C, int* done) {
+  int L = g->n_layers;
+  int last = -1;
+  for (int l = 0; l < L; ++l)
+    if (hi[l] >= 0) last = l;
+  double chi2 = 0.0;
+  int nh = 0;
+  int32_t st = 0;
+  *done = 0;
+  for (int l = 0; l <= last; ++l) {
+    double s2[6], C2[36];
+    memcpy(s2, s, sizeof s2);
+    memcpy(C2, C, sizeof C2);
+    /* no acceptance check in z: the hits are already assigned to the track */
+    st = propagate_impl(g, s2, C2, q, g->r[l], 0.0, NULL, NULL, NULL);
+    if (st) break;
+    if (hi[l] >= 0) {
+      double c2;
+      const double* hp = hit_pos + 3 * (int64_t)hi[l];
+      const double* hc = hit_cov + 9 * (int64_t)hi[l];
+      st = or_update_one(s2, C2, hp, hc, &c2, 0);
+      if (st) break;
+      chi2 += c2;
+      nh += 1;
+    }
+    memcpy(s, s2, sizeof s2);
+    memcpy(C, C2, sizeof C2);
+    if (rows_s) {
+      memcpy(rows_s + 6 * l, s, sizeof s2);
+      memcpy(rows_C + 36 * l, C, sizeof C2);
+    }
+    *done = l + 1;
+    if (l < last) {
+      st = material_impl(g, l, s2, C2, NULL);
+      if (st) break;
+      memcpy(s, s2, sizeof s2);
+      memcpy(C, C2, sizeof C2);
+    }
+  }
+  *chi2_out = chi2;
+  *nhits_out = nh;
+  return st;
+}
+
 int32_t or_fit(const or_geometry* g, int64_t n, const double* state_in, const double* cov_in, const int8_t* q,
                const int32_t* hit_idx, const double* hit_pos, const double* hit_cov, double* state_out,
                double* cov_out, double* chi2_out, int32_t* nhits_out, int32_t* status_out) {
@@ -402,42 +455,159 @@ int32_t or_fit(const or_geometry* g, int64_t n, const double* state_in, const do
     double s[6], C[36];
     memcpy(s, state_in + 6 * i, sizeof s);
     memcpy(C, cov_in + 36 * i, sizeof C);
-    const int32_t* hi = hit_idx + (int64_t)L * i;
-    int last = -1;
-    for (int l = 0; l < L; ++l)
-      if (hi[l] >= 0) last = l;
-    double chi2 = 0.0;
-    int nh = 0;
-    int32_t st = 0;
-    for (int l = 0; l <= last; ++l) {
-      double s2[6], C2[36];
-      memcpy(s2, s, sizeof s);
-      memcpy(C2, C, sizeof C);
-      /* no acceptance check in z: the hits are already assigned to the track */
-      st = propagate_impl(g, s2, C2, q[i], g->r[l], 0.0, NULL, NULL, NULL);
-      if (st) break;
-      if (hi[l] >= 0) {
-        double c2;
-        const double* hp = hit_pos + 3 * (int64_t)hi[l];
-        const double* hc = hit_cov + 9 * (int64_t)hi[l];
-        st = or_update_one(s2, C2, hp, hc, &c2, 0);
-        if (st) break;
-        chi2 += c2;
-        nh += 1;
-      }
-      memcpy(s, s2, sizeof s);
-      memcpy(C, C2, sizeof C);
-      if (l < last) {
-        st = material_impl(g, l, s2, C2, NULL);
-        if (st) break;
-        memcpy(s, s2, sizeof s);
-        memcpy(C, C2, sizeof C);
-      }
-    }
+    int done;
+    status_out[i] = fit_track(g, s, C, q[i], hit_idx + (int64_t)L * i, hit_pos, hit_cov, chi2_out + i,
+                              nhits_out + i, NULL, NULL, &done);
     memcpy(state_out + 6 * i, s, sizeof s);
     memcpy(cov_out + 36 * i, C, sizeof C);
-    chi2_out[i] = chi2;
-    nhits_out[i] = nh;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Smoother: the backward pass after the fit that gives every layer the
+ * estimate from all of the track's hits (a Kalman filter followed by a
+ * smoother is the paper's final fit of a found track, Sec. 2).  It is the
+ * Rauch-Tung-Striebel recursion, run outside in from the last hit layer:
+ *   A_l   = Cf_l F_l^T Cp_{l+1}^+
+ *   xs_l  = xf_l + A_l (xs_{l+1} - xp_{l+1})
+ *   Cs_l  = Cf_l + A_l (Cs_{l+1} - Cp_{l+1}) A_l^T
+ * with xf, Cf the filtered and xp, Cp the predicted estimates and F_l the
+ * derivative of the step from layer l to l+1 (material of layer l, then the
+ * crossing): F = J diag(1, 1, 1, f, f, f), f the momentum ratio of the energy
+ * loss, J the surface-constrained Jacobian.  A prediction on a cylinder has no
+ * variance along the radial direction of its position, so Cp is singular and
+ * its inverse is replaced by the Moore-Penrose pseudo-inverse on the surface.
+ * ---------------------------------------------------------------------- */
+
+/* Cholesky factor A = L L^T of an n x n symmetric matrix (lower triangle
+ * read); 0 unless A is positive definite. */
+static int chol_n(int n, const double* A, double* L) {
+  memset(L, 0, sizeof(double) * n * n);
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+    if (!(d > 0.0)) return 0;
+    L[j * n + j] = sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = v / L[j * n + j];
+    }
+  }
+  return 1;
+}
+
+/* b <- A^-1 b for A = L L^T */
+static void chol_solve_n(int n, const double* L, double* b) {
+  for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < i; ++k) b[i] -= L[i * n + k] * b[k];
+    b[i] /= L[i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    for (int k = i + 1; k < n; ++k) b[i] -= L[k * n + i] * b[k];
+    b[i] /= L[i * n + i];
+  }
+}
+
+int32_t or_surface_pinv(const double* C, double x, double y, double* Cp) {
+  double r = hypot(x, y);
+  if (!(r > 0.0)) return 0;
+  /* P: rows (tangent, z, px, py, pz), orthonormal, orthogonal to (x, y, 0, 0, 0, 0) */
+  double P[30];
+  memset(P, 0, sizeof P);
+  P[0 * 6 + 0] = -y / r;
+  P[0 * 6 + 1] = x / r;
+  for (int k = 1; k < 5; ++k) P[k * 6 + (k + 1)] = 1.0;
+  double PC[30], S[25], Lf[25];
+  mat_mul(5, 6, 6, P, C, PC);
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 6; ++k) acc += PC[i * 6 + k] * P[j * 6 + k];
+      S[i * 5 + j] = acc;
+    }
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < i; ++j) S[j * 5 + i] = S[i * 5 + j] = 0.5 * (S[i * 5 + j] + S[j * 5 + i]);
+  if (!chol_n(5, S, Lf)) return 0;
+  /* Sinv P, column by column of P */
+  double SiP[30];
+  for (int c = 0; c < 6; ++c) {
+    double b[5];
+    for (int i = 0; i < 5; ++i) b[i] = P[i * 6 + c];
+    chol_solve_n(5, Lf, b);
+    for (int i = 0; i < 5; ++i) SiP[i * 6 + c] = b[i];
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 5; ++k) acc += P[k * 6 + i] * SiP[k * 6 + j];
+      Cp[i * 6 + j] = acc;
+    }
+  symmetrize6(Cp);
+  return 1;
+}
+
+void or_rts_step(const double* xf, const double* Cf, const double* F, const double* xp, const double* Cp,
+                 const double* Cp_inv, const double* xs_next, const double* Cs_next, double* xs, double* Cs) {
+  double Ft[36], CfFt[36], A[36], At[36], M[36], AM[36], AMAt[36];
+  mat_transpose6(F, Ft);
+  mat_mul(6, 6, 6, Cf, Ft, CfFt);
+  mat_mul(6, 6, 6, CfFt, Cp_inv, A);
+  double d[6];
+  for (int i = 0; i < 6; ++i) d[i] = xs_next[i] - xp[i];
+  for (int i = 0; i < 6; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < 6; ++k) acc += A[i * 6 + k] * d[k];
+    xs[i] = xf[i] + acc;
+  }
+  for (int k = 0; k < 36; ++k) M[k] = Cs_next[k] - Cp[k];
+  mat_transpose6(A, At);
+  mat_mul(6, 6, 6, A, M, AM);
+  mat_mul(6, 6, 6, AM, At, AMAt);
+  for (int k = 0; k < 36; ++k) Cs[k] = Cf[k] + AMAt[k];
+  symmetrize6(Cs);
+}
+
+int32_t or_smooth(const or_geometry* g, int64_t n, const double* state_in, const double* cov_in, const int8_t* q,
+                  const int32_t* hit_idx, const double* hit_pos, const double* hit_cov, double* state_out,
+                  double* cov_out, int32_t* status_out) {
+  if (!g || n < 0) return -1;
+  int L = g->n_layers;
+  for (int64_t i = 0; i < n; ++i) {
+    double s[6], C[36], chi2;
+    int32_t nh;
+    int done;
+    double* rs = state_out + (int64_t)6 * L * i;
+    double* rc = cov_out + (int64_t)36 * L * i;
+    for (int k = 0; k < 6 * L; ++k) rs[k] = NAN;
+    for (int k = 0; k < 36 * L; ++k) rc[k] = NAN;
+    memcpy(s, state_in + 6 * i, sizeof s);
+    memcpy(C, cov_in + 36 * i, sizeof C);
+    int32_t st = fit_track(g, s, C, q[i], hit_idx + (int64_t)L * i, hit_pos, hit_cov, &chi2, &nh, rs, rc, &done);
+    /* the last row is already smoothed (it has seen every hit); a failed fit keeps its filtered rows */
+    for (int l = done - 2; st == 0 && l >= 0; --l) {
+      double x[6], Cx[36], J[36], F[36], Cpi[36];
+      memcpy(x, rs + 6 * l, sizeof x);
+      memcpy(Cx, rc + 36 * l, sizeof Cx);
+      double p0 = sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
+      /* the same steps the filter took from this layer to the next */
+      st = material_impl(g, l, x, Cx, NULL);
+      if (st) break;
+      double f = sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]) / p0;
+      st = propagate_impl(g, x, Cx, q[i], g->r[l + 1], 0.0, J, NULL, NULL);
+      if (st) break;
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) F[a * 6 + b] = J[a * 6 + b] * (b >= 3 ? f : 1.0);
+      if (!or_surface_pinv(Cx, x[0], x[1], Cpi)) {
+        st = OR_NOT_PD;
+        break;
+      }
+      double xs[6], Cs[36];
+      or_rts_step(rs + 6 * l, rc + 36 * l, F, x, Cx, Cpi, rs + 6 * (l + 1), rc + 36 * (l + 1), xs, Cs);
+      memcpy(rs + 6 * l, xs, sizeof xs);
+      memcpy(rc + 36 * l, Cs, sizeof Cs);
+    }
     status_out[i] = st;
   }
   return 0;

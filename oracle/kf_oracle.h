@@ -70,6 +70,25 @@ int32_t or_fit(const or_geometry* g, int64_t n, const double* state_in, const do
                const int32_t* hit_idx, const double* hit_pos, const double* hit_cov, double* state_out,
                double* cov_out, double* chi2_out, int32_t* nhits_out, int32_t* status_out);
 
+/* Smoother (Rauch-Tung-Striebel backward pass after the fit).  The forward
+ * pass is or_fit's; state_out [n][L][6] and cov_out [n][L][36] receive, for
+ * every layer 0 .. last hit layer, the smoothed state at that layer (after its
+ * crossing and update, before its material).  Rows after the last hit layer
+ * are NaN.  A track whose fit fails (status_out != 0, or_fit's bits) is not
+ * smoothed: the rows of the layers its filter completed hold the filtered
+ * states, later rows NaN.  Returns 0 or a negative error. */
+int32_t or_smooth(const or_geometry* g, int64_t n, const double* state_in, const double* cov_in, const int8_t* q,
+                  const int32_t* hit_idx, const double* hit_pos, const double* hit_cov, double* state_out,
+                  double* cov_out, int32_t* status_out);
+/* Moore-Penrose pseudo-inverse Cp (36) of a 6x6 covariance C whose null space
+ * is the radial direction (x, y, 0, 0, 0, 0) of a position on a cylinder.
+ * Returns 0 unless C is positive definite on the orthogonal complement. */
+int32_t or_surface_pinv(const double* C, double x, double y, double* Cp);
+/* One backward step: A = Cf F^T Cp_inv, xs = xf + A (xs_next - xp),
+ * Cs = Cf + A (Cs_next - Cp) A^T (all 6-vectors and row-major 6x6). */
+void or_rts_step(const double* xf, const double* Cf, const double* F, const double* xp, const double* Cp,
+                 const double* Cp_inv, const double* xs_next, const double* Cs_next, double* xs, double* Cs);
+
 /* Hit binning per (event, layer): phi bin i_phi in [0, n_phi), eta bin in
  * [0, n_eta) over the layer's acceptance, bin id = i_eta * n_phi + i_phi.
  * layer_offsets[E*L+1]; bin_offsets[(E*L)*(nb+1)] absolute indices into the
