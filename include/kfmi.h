@@ -152,6 +152,45 @@ typedef struct {
 } kf_fit_args;
 int32_t kf_fit(kf_ctx* ctx, const kf_fit_args* args);
 
+/* Smoother (Sec. 2: a Kalman filter followed by a smoother is the final fit of
+ * a found track; it gives every layer the estimate from all of the track's
+ * hits).  The forward pass is kf_fit's; a Rauch-Tung-Striebel backward pass
+ * then runs from the last hit layer inward, with the pseudo-inverse of each
+ * prediction's covariance on its cylinder (a prediction has no radial
+ * variance).  Same inputs and layouts as kf_fit.  Outputs:
+ *   state_out [n_layers][6][ld], cov_out [n_layers][21][ld] (packed): for every
+ *     layer up to the track's last hit layer, the smoothed state at that layer
+ *     (after its crossing and update, before its material); NaN after it.
+ *     A track whose fit fails (status != 0) is not smoothed: the rows of the
+ *     layers its filter completed hold the filtered states, later rows NaN.
+ *   chi2_out, nhits_out (nullable): as kf_fit;  status_out: kf_fit's bits
+ *     (ST_NOT_PD also when a prediction's surface block is not positive
+ *     definite in the backward pass; rows above that layer are then smoothed,
+ *     the others filtered).
+ * The output arrays must not alias the inputs.  flags: KF_FIT_FP64 keeps the
+ * filter in double-precision registers; the gain is always formed in double
+ * precision.  Errors: KF_ERR_INVALID_ARG (sizes, null arrays, unknown flags),
+ * KF_ERR_GEOMETRY (no geometry set). */
+typedef struct {
+  int64_t n, ld;
+  const float* state_in;
+  const float* cov_in;
+  const int8_t* charge;
+  const int32_t* hit_idx;
+  int64_t ld_idx;
+  const float* hit_pos;
+  const float* hit_cov;
+  int64_t ldh;
+  float* state_out;
+  float* cov_out;
+  float* chi2_out;
+  int32_t* nhits_out;
+  int32_t* status_out;
+  uint32_t flags;
+  void* stream;
+} kf_smooth_args;
+int32_t kf_smooth(kf_ctx* ctx, const kf_smooth_args* args);
+
 
 /* ------------------------------------------------------------------------
  * Hit binning (Sec. 3: hits of each layer are placed into directionally

@@ -247,8 +247,10 @@ KF_DEV int32_t propagate(T s[6], T c[21], T a, T R, T zh) {
 
 // Thin scatterer (multiple scattering, Highland width, and mean energy loss)
 // for a track sitting on a layer of normal thickness xx0 radiation lengths.
+// f_out (nullable) receives the momentum ratio p'/p of the energy loss.
 template <typename T>
-KF_DEV int32_t material(T s[6], T c[21], T xx0, T eloss, T mass) {
+KF_DEV int32_t material(T s[6], T c[21], T xx0, T eloss, T mass, T* f_out = nullptr) {
+  if (f_out) *f_out = T(1);
   if (!(xx0 > T(0))) return 0;
   const T p2 = s[3] * s[3] + s[4] * s[4] + s[5] * s[5];
   const T ip = rsqrt_t(p2);
@@ -265,6 +267,7 @@ KF_DEV int32_t material(T s[6], T c[21], T xx0, T eloss, T mass) {
   if (!(E2 > mass)) return ST_STOPPED;
   const T pn = sqrt_t((E2 - mass) * (E2 + mass));
   const T f = div_t(pn, p);
+  if (f_out) *f_out = f;
 #pragma unroll
   for (int i = 3; i < 6; ++i) s[i] *= f;
 #pragma unroll

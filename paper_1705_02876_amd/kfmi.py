@@ -56,6 +56,18 @@ class kf_fit_args(C.Structure):
     ]
 
 
+class kf_smooth_args(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("ld", C.c_int64),
+        ("state_in", C.c_void_p), ("cov_in", C.c_void_p), ("charge", C.c_void_p),
+        ("hit_idx", C.c_void_p), ("ld_idx", C.c_int64),
+        ("hit_pos", C.c_void_p), ("hit_cov", C.c_void_p), ("ldh", C.c_int64),
+        ("state_out", C.c_void_p), ("cov_out", C.c_void_p), ("chi2_out", C.c_void_p),
+        ("nhits_out", C.c_void_p), ("status_out", C.c_void_p),
+        ("flags", C.c_uint32), ("stream", C.c_void_p),
+    ]
+
+
 _lib = None
 
 
@@ -82,6 +94,8 @@ def load_library(path=LIB_PATH):
     lib.kf_update.argtypes = [P, I64, I64, P, P, P, P, I64, P, P, C.c_uint32, P]
     lib.kf_fit.restype = I32
     lib.kf_fit.argtypes = [P, P]
+    lib.kf_smooth.restype = I32
+    lib.kf_smooth.argtypes = [P, P]
     _declare_more(lib)
     _lib = lib
     return lib
@@ -217,3 +231,30 @@ class Context:
             a.ld_res = residual_out.shape[1]
         a.stream = _stream(stream)
         _check(_lib.kf_fit(self.h, C.byref(a)))
+
+    def kf_smooth(self, state_in, cov_in, charge, hit_idx, hit_pos, hit_cov, state_out, cov_out, status_out,
+                  chi2_out=None, nhits_out=None, n=None, stream=None, fp64=False):
+        """state_out (n_layers, 6, ld), cov_out (n_layers, 21, ld): smoothed rows per layer."""
+        import torch
+        for t, dt, nm in ((state_in, torch.float32, "state_in"), (cov_in, torch.float32, "cov_in"),
+                          (charge, torch.int8, "charge"), (hit_idx, torch.int32, "hit_idx"),
+                          (hit_pos, torch.float32, "hit_pos"), (hit_cov, torch.float32, "hit_cov"),
+                          (state_out, torch.float32, "state_out"), (cov_out, torch.float32, "cov_out"),
+                          (chi2_out, torch.float32, "chi2_out"), (nhits_out, torch.int32, "nhits_out"),
+                          (status_out, torch.int32, "status_out")):
+            _dev(t, dt, nm)
+        ld = state_in.shape[1]
+        L = hit_idx.shape[0]
+        if tuple(state_out.shape) != (L, 6, ld) or tuple(cov_out.shape) != (L, 21, ld):
+            raise ValueError(f"state_out must be ({L}, 6, {ld}) and cov_out ({L}, 21, {ld})")
+        a = kf_smooth_args()
+        a.ld = ld
+        a.n = ld if n is None else n
+        a.state_in, a.cov_in, a.charge = _ptr(state_in), _ptr(cov_in), _ptr(charge)
+        a.hit_idx, a.ld_idx = _ptr(hit_idx), hit_idx.shape[1]
+        a.hit_pos, a.hit_cov, a.ldh = _ptr(hit_pos), _ptr(hit_cov), hit_pos.shape[1]
+        a.state_out, a.cov_out, a.chi2_out = _ptr(state_out), _ptr(cov_out), _ptr(chi2_out)
+        a.nhits_out, a.status_out = _ptr(nhits_out), _ptr(status_out)
+        a.flags = FIT_FP64 if fp64 else 0
+        a.stream = _stream(stream)
+        _check(_lib.kf_smooth(self.h, C.byref(a)))

@@ -11,7 +11,7 @@ from paper_1705_02876_amd import kfmi
 def test_header_declares_the_core_calls():
     syms = kfmi.header_symbols()
     for s in ("kf_ctx_create", "kf_ctx_destroy", "kf_last_error", "kf_set_geometry", "kf_propagate_to_r",
-              "kf_update", "kf_fit"):
+              "kf_update", "kf_fit", "kf_smooth"):
         assert s in syms
 
 
@@ -53,7 +53,8 @@ def test_struct_layouts_match_the_c_header(tmp_path):
     from paper_1705_02876_amd import kfmi_build as KB
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")
-    structs = {"kf_geometry": kfmi.kf_geometry, "kf_fit_args": kfmi.kf_fit_args, "kf_bin_args": KB.kf_bin_args,
+    structs = {"kf_geometry": kfmi.kf_geometry, "kf_fit_args": kfmi.kf_fit_args,
+               "kf_smooth_args": kfmi.kf_smooth_args, "kf_bin_args": KB.kf_bin_args,
                "kf_build_cfg": KB.kf_build_cfg, "kf_build_args": KB.kf_build_args}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{kfmi.HEADER}"', "int main(void) {"]
     for name, cls in structs.items():
