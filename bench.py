@@ -40,14 +40,23 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 FLOP_PER_LAYER = 638
 FLOP_PER_HIT = 427
 FLOP_PER_MATERIAL = 85
+# one smoother step back from a layer: the filter's step repeated (material, crossing, transport) and the gain
+FLOP_PER_SMOOTH_STEP = 2063
 # bytes the fit must move per track: state+cov in (27 f32) + charge (1) + hit index per layer (4 L)
 # + per hit position and packed covariance (9 f32) + state+cov out (27 f32) + chi2, nhits, status (12)
 def fit_bytes(n, L, n_hits_total):
     return n * (108 + 1 + 4 * L + 108 + 12) + 36 * n_hits_total
 
 
+# bytes the smoother must move per track: the fit's inputs and scalars, and every layer's row out (27 f32)
+def smooth_bytes(n, L, n_hits_total):
+    return n * (108 + 1 + 4 * L + 108 * L + 12) + 36 * n_hits_total
+
+
 KERNEL_SOURCES = {
     "fit_kernel": ("kf_fit.hip", "kf_device.hpp", "kf_internal.hpp"),
+    "smooth_fwd_kernel": ("kf_fit.hip", "kf_device.hpp", "kf_internal.hpp"),
+    "smooth_bwd_kernel": ("kf_fit.hip", "kf_device.hpp", "kf_internal.hpp"),
     "bin_kernel": ("kf_build.hip", "kf_device.hpp", "kf_internal.hpp"),
     "bin_fine_kernel": ("kf_build.hip", "kf_device.hpp", "kf_internal.hpp"),
     "build_persistent_kernel": ("kf_build.hip", "kf_device.hpp", "kf_mlp_device.hpp", "kf_internal.hpp"),
@@ -184,6 +193,45 @@ def cpu_baseline_build(prob, det32, max_seeds=300_000, N=6):
     return {"value": nseeds / dt, "unit": "seeds/s", "cores": cores, "kind": "oracle",
             "sample": f"first {ne} events ({nseeds} seeds) of the batched build workload, FP64 oracle binned "
                       f"build N={N}, {cores} host threads (each bins the sample's hits), {dt:.2f} s wall"}
+
+
+def smooth_leg(ctx, fp, t, L, reps=3, fp64=False):
+    """The smoother (the fit followed by the backward pass, every layer's smoothed row written) over the fit
+    workload, timed alone with HIP events on the launch stream.  FLOPs: the fit's, plus one backward step per
+    layer below each converged track's last hit layer."""
+    import torch
+    n = t["n"]
+    rows_s = torch.empty(L, 6, n, dtype=torch.float32, device="cuda")
+    rows_c = torch.empty(L, 21, n, dtype=torch.float32, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    def call():
+        ctx.kf_smooth(t["state"], t["cov"], t["q"], t["hidx"], t["hpos"], t["hcov"], rows_s, rows_c, st, fp64=fp64)
+
+    call()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        call()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ok = st.cpu().numpy() == 0
+    steps = int(np.maximum(fp.last_layer, 0)[ok].sum())
+    flop = fit_flops(fp) + FLOP_PER_SMOOTH_STEP * steps
+    byt = smooth_bytes(n, L, int((fp.hit_idx >= 0).sum()))
+    sec = ms * 1e-3
+    res = {"kernels": "smooth_fwd_kernel + smooth_bwd_kernel", "avg_ms": ms, "tracks_per_s": n / sec, "backward_steps": steps,
+           "flop": flop, "tflops": flop / sec / 1e12, "alu_frac": flop / sec / 1e12 / VALU_PEAK_TFLOPS,
+           "bytes": byt, "gbs": byt / sec / 1e9, "hbm_frac": byt / sec / 1e9 / HBM_PEAK_GBS,
+           "status_nonzero": int((~ok).sum()),
+           "note": "the bytes are the algorithmic ones (inputs once, every layer's row out once); the kernel also "
+                   "writes each filtered row and reads it back for the backward pass"}
+    del rows_s, rows_c
+    torch.cuda.empty_cache()
+    return res
 
 
 def physics_leg(ctx, bp, seeds, hits, bins, bout, cfg):
@@ -426,6 +474,7 @@ def main():
     ap.add_argument("--fit-fp64", action="store_true", help="double-precision registers in the fit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-window leg")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the end-to-end leg from pinned host memory")
+    ap.add_argument("--no-smoother", action="store_true", help="skip the smoother leg")
     ap.add_argument("--nsigma", type=float, default=2.5, help="learned window half width in network scales")
     ap.add_argument("--train-tracks", type=int, default=625_000, help="fit tracks whose residuals train the window")
     ap.add_argument("--train-steps", type=int, default=300)
@@ -619,6 +668,9 @@ def main():
                            "updates": int(counters[4])},
         "fit_status_nonzero": int((stat != 0).sum().item()),
     }
+    if not args.no_smoother:
+        out["smoother"] = smooth_leg(ctx, fp, dict(state=st_in, cov=cv_in, q=q, hidx=hidx, hpos=hpos, hcov=hcov, n=n),
+                                     L, fp64=args.fit_fp64)
     out["physics"] = physics_leg(ctx, bp, seeds, hits, bins, bout, cfg)
     if not args.no_pipeline:
         out["pipeline"] = pipeline_leg(ctx, bp, cfg, bout, bin_ms + build_ms)

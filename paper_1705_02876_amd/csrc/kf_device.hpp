@@ -513,6 +513,163 @@ KF_DEV int32_t update_on_layer(T s[6], T c[21], const float m[3], const float v[
 // q/pT, cot(theta), z/z_half, sin of the angle between the transverse momentum
 // and the radial direction, r_from/100, r_to/100, and the logs of the
 // predicted position's tangential and z standard deviations (cm).
+// ---- smoother: one Rauch-Tung-Striebel backward step,
+//   K = Cf F^T Cp^+,  xs_l = xf_l + K (xs_{l+1} - xp_{l+1}),  Cs_l = Cf_l + K (Cs_{l+1} - Cp_{l+1}) K^T,
+// with Cp^+ = P^T (P Cp P^T)^-1 P the pseudo-inverse on the cylinder (P: the orthonormal rows tangent, z, px,
+// py, pz) and F = J diag(1, 1, 1, f, f, f) the derivative of the filter's step from layer l to l+1.
+
+// y <- L^-1 y for the packed lower-triangular 5x5 factor L (row-major lower
+// triangle, tri(i, j)) with its reciprocal diagonal id.
+template <typename U>
+KF_DEV void fwd_subst5(const U Lf[15], const U id[5], U y[5]) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    U v = y[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= Lf[tri(i, k)] * y[k];
+    y[i] = v * id[i];
+  }
+}
+
+// One backward step of one track (precision U for the gain).  xs, cs hold the
+// smoothed state of layer l+1 on entry and of layer l on exit; xf, cf the
+// filtered state of layer l.  Returns 0 or a status bit (ST_NOT_PD: the
+// prediction's surface block is not positive definite).
+template <typename T, typename U>
+KF_DEV int32_t rts_step(const float xf[6], const float cf[21], T a, const Geom& g, int l,
+                                            float xs[6], float cs[21]) {
+  T xp[6], cp[21];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) xp[k] = T(xf[k]);
+#pragma unroll
+  for (int k = 0; k < 21; ++k) cp[k] = T(cf[k]);
+  // (in single precision these are the forward pass's own values and cannot fail; a double-precision
+  // filter reads back float32 rows, whose step could in principle fail where the filter's did not)
+  T f;
+  if (int32_t e = material(xp, cp, T(g.x_over_x0[l]), T(g.eloss_per_x0), T(g.mass), &f)) return e;
+  Prop<T> pr;
+  if (int32_t e = helix_to_r(xp, a, T(g.r[l + 1]), T(0), pr)) return e;
+  transport(cp, pr);
+  // surface frame at the prediction
+  const U px0 = U(pr.s[0]), py0 = U(pr.s[1]);
+  const U ir = rsqrt_pos(px0 * px0 + py0 * py0);
+  const U tx = -py0 * ir, ty = px0 * ir;
+  const U fu = U(f);
+  // rows of P J D over the columns (x, y, z, px, py, pz)
+  const U Rt[6] = {tx * U(pr.jx[0]) + ty * U(pr.jy[0]), tx * U(pr.jx[1]) + ty * U(pr.jy[1]), U(0),
+                   (tx * U(pr.jx[2]) + ty * U(pr.jy[2])) * fu, (tx * U(pr.jx[3]) + ty * U(pr.jy[3])) * fu, U(0)};
+  const U Rz[6] = {U(pr.jz[0]), U(pr.jz[1]), U(1), U(pr.jz[3]) * fu, U(pr.jz[4]) * fu, U(pr.jz[5]) * fu};
+  const U Rx[6] = {U(pr.jpx[0]), U(pr.jpx[1]), U(0), U(pr.jpx[2]) * fu, U(pr.jpx[3]) * fu, U(0)};
+  const U Ry[6] = {U(pr.jpy[0]), U(pr.jpy[1]), U(0), U(pr.jpy[2]) * fu, U(pr.jpy[3]) * fu, U(0)};
+  // S = P Cp P^T and its Cholesky factor
+  U Sm[15];
+  {
+    const U c00 = U(cp[0]), c10 = U(cp[1]), c11 = U(cp[2]);
+    Sm[0] = tx * tx * c00 + U(2) * tx * ty * c10 + ty * ty * c11;
+#pragma unroll
+    for (int r = 1; r < 5; ++r) {
+      Sm[tri(r, 0)] = tx * U(cp[tri(r + 1, 0)]) + ty * U(cp[tri(r + 1, 1)]);
+#pragma unroll
+      for (int q = 1; q <= r; ++q) Sm[tri(r, q)] = U(cp[tri(r + 1, q + 1)]);
+    }
+  }
+  U Lf[15], id[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    U d = Sm[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= Lf[tri(j, k)] * Lf[tri(j, k)];
+    if (!(d > U(0))) return ST_NOT_PD;
+    const U is = rsqrt_pos(d);
+    Lf[tri(j, j)] = d * is;
+    id[j] = is;
+#pragma unroll
+    for (int i = j + 1; i < 5; ++i) {
+      U v = Sm[tri(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= Lf[tri(i, k)] * Lf[tri(j, k)];
+      Lf[tri(i, j)] = v * is;
+    }
+  }
+  // v = L^-1 P (xs - xp)
+  U v[5];
+  v[0] = tx * (U(xs[0]) - U(pr.s[0])) + ty * (U(xs[1]) - U(pr.s[1]));
+#pragma unroll
+  for (int k = 1; k < 5; ++k) v[k] = U(xs[k + 1]) - U(pr.s[k + 1]);
+  fwd_subst5(Lf, id, v);
+  // N = L^-1 P (Cs - Cp) P^T L^-T
+  U N[15];
+  {
+    U Md[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Md[k] = U(cs[k]) - U(cp[k]);
+    U M5[5][5];
+    M5[0][0] = tx * tx * Md[0] + U(2) * tx * ty * Md[1] + ty * ty * Md[2];
+#pragma unroll
+    for (int r = 1; r < 5; ++r) {
+      M5[r][0] = M5[0][r] = tx * Md[tri(r + 1, 0)] + ty * Md[tri(r + 1, 1)];
+#pragma unroll
+      for (int q = 1; q <= r; ++q) M5[r][q] = M5[q][r] = Md[tri(r + 1, q + 1)];
+    }
+    // Y = L^-1 M5 column by column, then N = L^-1 Y^T (symmetric)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      U y[5] = {M5[0][c], M5[1][c], M5[2][c], M5[3][c], M5[4][c]};
+      fwd_subst5(Lf, id, y);
+#pragma unroll
+      for (int r = 0; r < 5; ++r) M5[r][c] = y[r];
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      U y[5] = {M5[c][0], M5[c][1], M5[c][2], M5[c][3], M5[c][4]};
+      fwd_subst5(Lf, id, y);
+#pragma unroll
+      for (int r = c; r < 5; ++r) N[tri(r, c)] = y[r];
+    }
+  }
+  // W = B L^-T, row i = L^-1 (P F Cf)[.][i]; then the smoothed state and covariance
+  U W[6][5];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    U cfi[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) cfi[k] = U(cf[i >= k ? tri(i, k) : tri(k, i)]);
+    U b[5] = {U(0), U(0), U(0), U(0), cfi[5] * fu};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      b[0] += cfi[k] * Rt[k];
+      b[1] += cfi[k] * Rz[k];
+      b[2] += cfi[k] * Rx[k];
+      b[3] += cfi[k] * Ry[k];
+    }
+    fwd_subst5(Lf, id, b);
+#pragma unroll
+    for (int r = 0; r < 5; ++r) W[i][r] = b[r];
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const U dx = W[i][0] * v[0] + W[i][1] * v[1] + W[i][2] * v[2] + W[i][3] * v[3] + W[i][4] * v[4];
+    xs[i] = float(U(xf[i]) + dx);
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    U wn[5];  // (W N)[i]
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      U acc = U(0);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) acc += W[i][q] * N[r >= q ? tri(r, q) : tri(q, r)];
+      wn[r] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      const U d = wn[0] * W[j][0] + wn[1] * W[j][1] + wn[2] * W[j][2] + wn[3] * W[j][3] + wn[4] * W[j][4];
+      cs[tri(i, j)] = float(U(cf[tri(i, j)]) + d);
+    }
+  }
+  return 0;
+}
+
 template <typename T>
 __device__ __forceinline__ void window_features(const T s[6], const T c[21], float q, float r_from, float r_to,
                                                 float zh, float f[8]) {

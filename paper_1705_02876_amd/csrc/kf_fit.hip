@@ -277,7 +277,12 @@ __device__ __forceinline__ void store_row(float* __restrict__ st, float* __restr
                                           const T s[6], const T c[21]) {
   float* sr = st + static_cast<int64_t>(l) * 6 * static_cast<int64_t>(ld);
   float* cr = cv + static_cast<int64_t>(l) * 21 * static_cast<int64_t>(ld);
-  store_track(sr, cr, ld, i, s, c);
+  // ordinary (cached) stores: the rows form 27 L strided streams, which non-temporal stores write back
+  // several times slower
+#pragma unroll
+  for (int k = 0; k < 6; ++k) *elem(sr + k * static_cast<int64_t>(ld), i) = static_cast<float>(s[k]);
+#pragma unroll
+  for (int k = 0; k < 21; ++k) *elem(cr + k * static_cast<int64_t>(ld), i) = static_cast<float>(c[k]);
 }
 
 template <typename I>
@@ -291,165 +296,16 @@ __device__ __forceinline__ void load_row(const float* st, const float* cv, I ld,
   for (int k = 0; k < 21; ++k) c[k] = *elem(cr + k * static_cast<int64_t>(ld), i);
 }
 
-// y <- L^-1 y for the packed lower-triangular 5x5 factor L (row-major lower
-// triangle, tri(i, j)) with its reciprocal diagonal id.
-__device__ __forceinline__ void fwd_subst5(const double Lf[15], const double id[5], double y[5]) {
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    double v = y[i];
-#pragma unroll
-    for (int k = 0; k < i; ++k) v -= Lf[tri(i, k)] * y[k];
-    y[i] = v * id[i];
-  }
-}
-
-// One backward step of one track (precision U for the gain).  xs, cs hold the
-// smoothed state of layer l+1 on entry and of layer l on exit; xf, cf the
-// filtered state of layer l.  Returns 0 or a status bit (ST_NOT_PD: the
-// prediction's surface block is not positive definite).
-template <typename T, typename U>
-__device__ __forceinline__ int32_t rts_step(const float xf[6], const float cf[21], T a, const Geom& g, int l,
-                                            float xs[6], float cs[21]) {
-  T xp[6], cp[21];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) xp[k] = T(xf[k]);
-#pragma unroll
-  for (int k = 0; k < 21; ++k) cp[k] = T(cf[k]);
-  // (in single precision these are the forward pass's own values and cannot fail; a double-precision
-  // filter reads back float32 rows, whose step could in principle fail where the filter's did not)
-  T f;
-  if (int32_t e = material(xp, cp, T(g.x_over_x0[l]), T(g.eloss_per_x0), T(g.mass), &f)) return e;
-  Prop<T> pr;
-  if (int32_t e = helix_to_r(xp, a, T(g.r[l + 1]), T(0), pr)) return e;
-  transport(cp, pr);
-  // surface frame at the prediction
-  const U px0 = U(pr.s[0]), py0 = U(pr.s[1]);
-  const U ir = rsqrt_pos(px0 * px0 + py0 * py0);
-  const U tx = -py0 * ir, ty = px0 * ir;
-  const U fu = U(f);
-  // rows of P J D over the columns (x, y, z, px, py, pz)
-  const U Rt[6] = {tx * U(pr.jx[0]) + ty * U(pr.jy[0]), tx * U(pr.jx[1]) + ty * U(pr.jy[1]), U(0),
-                   (tx * U(pr.jx[2]) + ty * U(pr.jy[2])) * fu, (tx * U(pr.jx[3]) + ty * U(pr.jy[3])) * fu, U(0)};
-  const U Rz[6] = {U(pr.jz[0]), U(pr.jz[1]), U(1), U(pr.jz[3]) * fu, U(pr.jz[4]) * fu, U(pr.jz[5]) * fu};
-  const U Rx[6] = {U(pr.jpx[0]), U(pr.jpx[1]), U(0), U(pr.jpx[2]) * fu, U(pr.jpx[3]) * fu, U(0)};
-  const U Ry[6] = {U(pr.jpy[0]), U(pr.jpy[1]), U(0), U(pr.jpy[2]) * fu, U(pr.jpy[3]) * fu, U(0)};
-  // S = P Cp P^T and its Cholesky factor
-  U Sm[15];
-  {
-    const U c00 = U(cp[0]), c10 = U(cp[1]), c11 = U(cp[2]);
-    Sm[0] = tx * tx * c00 + U(2) * tx * ty * c10 + ty * ty * c11;
-#pragma unroll
-    for (int r = 1; r < 5; ++r) {
-      Sm[tri(r, 0)] = tx * U(cp[tri(r + 1, 0)]) + ty * U(cp[tri(r + 1, 1)]);
-#pragma unroll
-      for (int q = 1; q <= r; ++q) Sm[tri(r, q)] = U(cp[tri(r + 1, q + 1)]);
-    }
-  }
-  U Lf[15], id[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    U d = Sm[tri(j, j)];
-#pragma unroll
-    for (int k = 0; k < j; ++k) d -= Lf[tri(j, k)] * Lf[tri(j, k)];
-    if (!(d > U(0))) return ST_NOT_PD;
-    const U is = rsqrt_pos(d);
-    Lf[tri(j, j)] = d * is;
-    id[j] = is;
-#pragma unroll
-    for (int i = j + 1; i < 5; ++i) {
-      U v = Sm[tri(i, j)];
-#pragma unroll
-      for (int k = 0; k < j; ++k) v -= Lf[tri(i, k)] * Lf[tri(j, k)];
-      Lf[tri(i, j)] = v * is;
-    }
-  }
-  // v = L^-1 P (xs - xp)
-  U v[5];
-  v[0] = tx * (U(xs[0]) - U(pr.s[0])) + ty * (U(xs[1]) - U(pr.s[1]));
-#pragma unroll
-  for (int k = 1; k < 5; ++k) v[k] = U(xs[k + 1]) - U(pr.s[k + 1]);
-  fwd_subst5(Lf, id, v);
-  // N = L^-1 P (Cs - Cp) P^T L^-T
-  U N[15];
-  {
-    U Md[21];
-#pragma unroll
-    for (int k = 0; k < 21; ++k) Md[k] = U(cs[k]) - U(cp[k]);
-    U M5[5][5];
-    M5[0][0] = tx * tx * Md[0] + U(2) * tx * ty * Md[1] + ty * ty * Md[2];
-#pragma unroll
-    for (int r = 1; r < 5; ++r) {
-      M5[r][0] = M5[0][r] = tx * Md[tri(r + 1, 0)] + ty * Md[tri(r + 1, 1)];
-#pragma unroll
-      for (int q = 1; q <= r; ++q) M5[r][q] = M5[q][r] = Md[tri(r + 1, q + 1)];
-    }
-    // Y = L^-1 M5 column by column, then N = L^-1 Y^T (symmetric)
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      U y[5] = {M5[0][c], M5[1][c], M5[2][c], M5[3][c], M5[4][c]};
-      fwd_subst5(Lf, id, y);
-#pragma unroll
-      for (int r = 0; r < 5; ++r) M5[r][c] = y[r];
-    }
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      U y[5] = {M5[c][0], M5[c][1], M5[c][2], M5[c][3], M5[c][4]};
-      fwd_subst5(Lf, id, y);
-#pragma unroll
-      for (int r = c; r < 5; ++r) N[tri(r, c)] = y[r];
-    }
-  }
-  // W = B L^-T, row i = L^-1 (P F Cf)[.][i]; then the smoothed state and covariance
-  U W[6][5];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    U cfi[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) cfi[k] = U(cf[i >= k ? tri(i, k) : tri(k, i)]);
-    U b[5] = {U(0), U(0), U(0), U(0), cfi[5] * fu};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      b[0] += cfi[k] * Rt[k];
-      b[1] += cfi[k] * Rz[k];
-      b[2] += cfi[k] * Rx[k];
-      b[3] += cfi[k] * Ry[k];
-    }
-    fwd_subst5(Lf, id, b);
-#pragma unroll
-    for (int r = 0; r < 5; ++r) W[i][r] = b[r];
-  }
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const U dx = W[i][0] * v[0] + W[i][1] * v[1] + W[i][2] * v[2] + W[i][3] * v[3] + W[i][4] * v[4];
-    xs[i] = float(U(xf[i]) + dx);
-  }
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    U wn[5];  // (W N)[i]
-#pragma unroll
-    for (int r = 0; r < 5; ++r) {
-      U acc = U(0);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) acc += W[i][q] * N[r >= q ? tri(r, q) : tri(q, r)];
-      wn[r] = acc;
-    }
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      const U d = wn[0] * W[j][0] + wn[1] * W[j][1] + wn[2] * W[j][2] + wn[3] * W[j][3] + wn[4] * W[j][4];
-      cs[tri(i, j)] = float(U(cf[tri(i, j)]) + d);
-    }
-  }
-  return 0;
-}
-
+// Forward pass: the fit, each completed layer's filtered state stored in its row, NaN in the rows it did not
+// reach.  Writes chi2, nhits (nullable) and status.
 template <typename T, typename I>
-__device__ __forceinline__ void smooth_body(I n, I ld, const float* state_in, const float* cov_in,
-                                            const int8_t* __restrict__ charge, const int32_t* __restrict__ hit_idx,
-                                            I ld_idx, const float* __restrict__ hit_pos,
-                                            const float* __restrict__ hit_cov, I ldh, float* state_out,
-                                            float* cov_out, float* __restrict__ chi2_out,
-                                            int32_t* __restrict__ nhits_out, int32_t* __restrict__ status_out,
-                                            const Geom& g) {
+__device__ __forceinline__ void smooth_fwd_body(I n, I ld, const float* state_in, const float* cov_in,
+                                                const int8_t* __restrict__ charge, const int32_t* __restrict__ hit_idx,
+                                                I ld_idx, const float* __restrict__ hit_pos,
+                                                const float* __restrict__ hit_cov, I ldh, float* state_out,
+                                                float* cov_out, float* __restrict__ chi2_out,
+                                                int32_t* __restrict__ nhits_out, int32_t* __restrict__ status_out,
+                                                const Geom& g) {
   const I i = static_cast<I>(blockIdx.x) * static_cast<I>(blockDim.x) + static_cast<I>(threadIdx.x);
   if (i >= n) return;
   const int L = g.n_layers;
@@ -463,62 +319,96 @@ __device__ __forceinline__ void smooth_body(I n, I ld, const float* state_in, co
       last = l;
       break;
     }
-  // forward: the fit, with each completed layer's filtered state stored in its row
+  // Every layer's row is written at that layer's iteration by every lane of the wave in one store
+  // instruction (the filtered state, or NaN where the lane's filter did not complete the layer), so each
+  // cache line of a row is written whole, once.
   T chi2 = T(0);
   int32_t nh = 0, st = 0;
-  int done = 0;
+  bool alive = true;  // no step has failed and the layer is not beyond the last hit layer
   int32_t h_nxt = last >= 0 ? *elem(hit_idx, i) : -1;
-  for (int l = 0; l <= last; ++l) {
-    const int32_t h_cur = h_nxt;
-    float m[3], v[6];
-    load_hit(hit_pos, hit_cov, ldh, h_cur >= 0 ? h_cur : 0, m, v);
-    h_nxt = (l + 1 <= last) ? *elem(hit_idx + (l + 1) * static_cast<int64_t>(ld_idx), i) : -1;
-    st = propagate(s, c, a, T(g.r[l]), T(0));
-    if (st) break;
-    if (h_cur >= 0) {
-      T dc2;
-      st = update_on_layer<T, double>(s, c, m, v, dc2);
-      if (st) break;
-      chi2 += dc2;
-      nh += 1;
+  for (int l = 0; l < L; ++l) {
+    alive = alive && l <= last;
+    bool row_ok = false;
+    if (alive) {
+      const int32_t h_cur = h_nxt;
+      float m[3], v[6];
+      load_hit(hit_pos, hit_cov, ldh, h_cur >= 0 ? h_cur : 0, m, v);
+      h_nxt = (l + 1 <= last) ? *elem(hit_idx + (l + 1) * static_cast<int64_t>(ld_idx), i) : -1;
+      st = propagate(s, c, a, T(g.r[l]), T(0));
+      if (!st && h_cur >= 0) {
+        T dc2;
+        st = update_on_layer<T, double>(s, c, m, v, dc2);
+        if (!st) {
+          chi2 += dc2;
+          nh += 1;
+        }
+      }
+      row_ok = st == 0;
     }
-    store_row(state_out, cov_out, ld, l, i, s, c);
-    done = l + 1;
-    if (l < last) {
-      st = material(s, c, T(g.x_over_x0[l]), T(g.eloss_per_x0), T(g.mass));
-      if (st) break;
+    {
+      T rs[6], rc[21];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rs[k] = row_ok ? s[k] : T(NAN);
+#pragma unroll
+      for (int k = 0; k < 21; ++k) rc[k] = row_ok ? c[k] : T(NAN);
+      store_row(state_out, cov_out, ld, l, i, rs, rc);
     }
-  }
-  // rows the filter did not reach
-  {
-    T nan6[6], nan21[21];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) nan6[k] = T(NAN);
-#pragma unroll
-    for (int k = 0; k < 21; ++k) nan21[k] = T(NAN);
-    for (int l = done; l < L; ++l) store_row(state_out, cov_out, ld, l, i, nan6, nan21);
-  }
-  // backward, over a layer index that is uniform across the wave
-  if (st == 0 && done >= 2) {
-    float xs[6], cs[21];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) xs[k] = float(s[k]);
-#pragma unroll
-    for (int k = 0; k < 21; ++k) cs[k] = float(c[k]);
-    // the last row holds the filtered state of the last layer, already the smoothed one (float32 in HBM)
-    for (int l = L - 2; l >= 0; --l) {
-      if (l >= done - 1) continue;
-      float xf[6], cf[21];
-      load_row(state_out, cov_out, ld, l, i, xf, cf);
-      st = rts_step<T, double>(xf, cf, a, g, l, xs, cs);
-      if (st) break;
-      store_track(state_out + static_cast<int64_t>(l) * 6 * static_cast<int64_t>(ld),
-                  cov_out + static_cast<int64_t>(l) * 21 * static_cast<int64_t>(ld), ld, i, xs, cs);
+    if (alive) {
+      if (!row_ok)
+        alive = false;
+      else if (l < last) {
+        st = material(s, c, T(g.x_over_x0[l]), T(g.eloss_per_x0), T(g.mass));
+        if (st) alive = false;
+      }
     }
   }
   if (chi2_out) *elem(chi2_out, i) = static_cast<float>(chi2);
   if (nhits_out) *elem(nhits_out, i) = nh;
   *elem(status_out, i) = st;
+}
+
+// Backward pass of the tracks whose fit converged: from the last hit layer's row (filtered there = smoothed)
+// inward, over a layer index that is uniform across the wave.  A failing step (not positive definite) sets the
+// status and leaves the rows below it filtered.
+template <typename T, typename I>
+__device__ __forceinline__ void smooth_bwd_body(I n, I ld, const int8_t* __restrict__ charge,
+                                                const int32_t* __restrict__ hit_idx, I ld_idx, float* state_out,
+                                                float* cov_out, int32_t* __restrict__ status_out, const Geom& g) {
+  const I i = static_cast<I>(blockIdx.x) * static_cast<I>(blockDim.x) + static_cast<I>(threadIdx.x);
+  if (i >= n) return;
+  if (*elem(status_out, i) != 0) return;
+  const int L = g.n_layers;
+  int last = -1;
+  for (int l = L - 1; l >= 0; --l)
+    if (*elem(hit_idx + l * static_cast<int64_t>(ld_idx), i) >= 0) {
+      last = l;
+      break;
+    }
+  if (last < 1) return;
+  const int8_t qi = *elem(charge, i);
+  const T a = T(-static_cast<double>(qi) * kCLight * g.bz);
+  float xs[6], cs[21];
+  load_row(state_out, cov_out, ld, last, i, xs, cs);
+  // The filtered row of the next layer inward is fetched while this layer's step computes (one wave per SIMD
+  // leaves nothing else to cover the latency).  Every lane fetches at every layer index, also where it has
+  // no step (rows of every layer exist: NaN above the last hit layer), so the fetch needs no branch.
+  float xn[6], cn[21];
+  load_row(state_out, cov_out, ld, L - 2, i, xn, cn);
+  for (int l = L - 2; l >= 0; --l) {
+    float xf[6], cf[21];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) xf[k] = xn[k];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) cf[k] = cn[k];
+    if (l >= 1) load_row(state_out, cov_out, ld, l - 1, i, xn, cn);
+    if (l >= last) continue;
+    const int32_t st = rts_step<T, double>(xf, cf, a, g, l, xs, cs);
+    if (st) {
+      *elem(status_out, i) = st;
+      return;
+    }
+    store_row(state_out, cov_out, ld, l, i, xs, cs);
+  }
 }
 
 #define KF_SMOOTH_PARAMS                                                                                          \
@@ -533,10 +423,32 @@ __device__ __forceinline__ void smooth_body(I n, I ld, const float* state_in, co
   static_cast<uint32_t>(n), static_cast<uint32_t>(ld), state_in, cov_in, charge, hit_idx,                         \
       static_cast<uint32_t>(ld_idx), hit_pos, hit_cov, static_cast<uint32_t>(ldh), state_out, cov_out, chi2_out, \
       nhits_out, status_out, g
+#define KF_SMOOTH_BWD_PARAMS                                                                                      \
+  int64_t n, int64_t ld, const int8_t *__restrict__ charge, const int32_t *__restrict__ hit_idx, int64_t ld_idx, \
+      float *state_out, float *cov_out, int32_t *__restrict__ status_out, Geom g
+#define KF_SMOOTH_BWD_ARGS n, ld, charge, hit_idx, ld_idx, state_out, cov_out, status_out, g
+#define KF_SMOOTH_BWD_ARGS32                                                                                      \
+  static_cast<uint32_t>(n), static_cast<uint32_t>(ld), charge, hit_idx, static_cast<uint32_t>(ld_idx),           \
+      state_out, cov_out, status_out, g
 
-__global__ void __launch_bounds__(256) smooth_kernel(KF_SMOOTH_PARAMS) { smooth_body<float, uint32_t>(KF_SMOOTH_ARGS32); }
-__global__ void __launch_bounds__(256) smooth_kernel_i64(KF_SMOOTH_PARAMS) { smooth_body<float, int64_t>(KF_SMOOTH_ARGS); }
-__global__ void __launch_bounds__(256) smooth_kernel_f64(KF_SMOOTH_PARAMS) { smooth_body<double, int64_t>(KF_SMOOTH_ARGS); }
+// the forward pass has the fit's register needs and its occupancy; the backward pass's double-precision
+// gain fits two waves per SIMD (at most 256 registers, no spills) in single precision
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) smooth_fwd_kernel(KF_SMOOTH_PARAMS) {
+  smooth_fwd_body<float, uint32_t>(KF_SMOOTH_ARGS32);
+}
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) smooth_fwd_kernel_i64(KF_SMOOTH_PARAMS) {
+  smooth_fwd_body<float, int64_t>(KF_SMOOTH_ARGS);
+}
+__global__ void __launch_bounds__(256) smooth_fwd_kernel_f64(KF_SMOOTH_PARAMS) { smooth_fwd_body<double, int64_t>(KF_SMOOTH_ARGS); }
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) smooth_bwd_kernel(KF_SMOOTH_BWD_PARAMS) {
+  smooth_bwd_body<float, uint32_t>(KF_SMOOTH_BWD_ARGS32);
+}
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) smooth_bwd_kernel_i64(KF_SMOOTH_BWD_PARAMS) {
+  smooth_bwd_body<float, int64_t>(KF_SMOOTH_BWD_ARGS);
+}
+__global__ void __launch_bounds__(256) smooth_bwd_kernel_f64(KF_SMOOTH_BWD_PARAMS) {
+  smooth_bwd_body<double, int64_t>(KF_SMOOTH_BWD_ARGS);
+}
 
 }  // namespace
 
@@ -680,11 +592,17 @@ int32_t kf_smooth(kf_ctx* ctx, const kf_smooth_args* a) {
     return set_error(KF_ERR_INVALID_ARG, "null array");
   const int64_t ext = std::max({static_cast<int64_t>(L) * 21 * a->ld, static_cast<int64_t>(L) * a->ld_idx, 6 * a->ldh});
   const bool narrow = ext < (int64_t(1) << 30);
-  auto kern = (a->flags & KF_FIT_FP64) ? smooth_kernel_f64 : (narrow ? smooth_kernel : smooth_kernel_i64);
-  kern<<<kfh::grid_for(a->n, 256), 256, 0, kfh::stream_of(a->stream)>>>(
-      a->n, a->ld, a->state_in, a->cov_in, a->charge, a->hit_idx, a->ld_idx, a->hit_pos, a->hit_cov, a->ldh,
-      a->state_out, a->cov_out, a->chi2_out, a->nhits_out, a->status_out, ctx->dgeom);
-  return kfh::check_hip(hipGetLastError(), "smooth_kernel launch");
+  const bool f64 = (a->flags & KF_FIT_FP64) != 0;
+  auto fwd = f64 ? smooth_fwd_kernel_f64 : (narrow ? smooth_fwd_kernel : smooth_fwd_kernel_i64);
+  auto bwd = f64 ? smooth_bwd_kernel_f64 : (narrow ? smooth_bwd_kernel : smooth_bwd_kernel_i64);
+  hipStream_t sm = kfh::stream_of(a->stream);
+  fwd<<<kfh::grid_for(a->n, 256), 256, 0, sm>>>(a->n, a->ld, a->state_in, a->cov_in, a->charge, a->hit_idx,
+                                                a->ld_idx, a->hit_pos, a->hit_cov, a->ldh, a->state_out, a->cov_out,
+                                                a->chi2_out, a->nhits_out, a->status_out, ctx->dgeom);
+  if (int32_t rc = kfh::check_hip(hipGetLastError(), "smooth_fwd_kernel launch")) return rc;
+  bwd<<<kfh::grid_for(a->n, 256), 256, 0, sm>>>(a->n, a->ld, a->charge, a->hit_idx, a->ld_idx, a->state_out,
+                                                a->cov_out, a->status_out, ctx->dgeom);
+  return kfh::check_hip(hipGetLastError(), "smooth_bwd_kernel launch");
 }
 
 }  // extern "C"

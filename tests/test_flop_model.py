@@ -66,5 +66,6 @@ def test_bench_flop_constants_are_the_source_counts(counts):
     assert bench.FLOP_PER_LAYER == counts["propagate"][0]
     assert bench.FLOP_PER_MATERIAL == counts["material"][0]
     assert bench.FLOP_PER_HIT == counts["update"][0]
+    assert bench.FLOP_PER_SMOOTH_STEP == counts["smooth_step"][0]
     assert bench.BUILD_FLOP_CHI2 == counts["chi2"][0]
     assert bench.BUILD_FLOP_STEP == counts["propagate"][0] + counts["material"][0] + counts["local_pred"][0]
