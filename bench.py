@@ -292,7 +292,8 @@ def pipeline_leg(ctx, bp, cfg, bout, resident_ms, n_chunks=4, reps=3):
     n_slots = 3
     slots = [{k: torch.empty(cap[k], dtype=dt[k], device="cuda") for k in cap} for _ in range(n_slots)]
     max_nh, max_ns = max(c["nh"] for c in host), max(c["ns"] for c in host)
-    bws = torch.empty(max(kfmi.load_library().kf_bin_hits_workspace_size(max_nh), 4), dtype=torch.uint8,
+    bws = torch.empty(max(kfmi.load_library().kf_bin_hits_workspace_size(max_nh, max(c["ne"] for c in host)), 4),
+                      dtype=torch.uint8,
                       device="cuda")
     ws = torch.empty(max(KB.workspace_bytes(cfg, max(c["ne"] for c in host), max_ns), 1), dtype=torch.uint8,
                      device="cuda")
@@ -522,7 +523,7 @@ def main():
     seeds, hits = KB.upload_problem(bp)
     N = 6
     mode = KB.BUILD_PERSISTENT if args.build_mode == "persistent" else KB.BUILD_TILED
-    bws_bytes = kfmi.load_library().kf_bin_hits_workspace_size(hits["pos"].shape[1])
+    bws_bytes = kfmi.load_library().kf_bin_hits_workspace_size(hits["pos"].shape[1], bp.n_events)
     bws = torch.empty(max(bws_bytes, 4), dtype=torch.uint8, device=dev)
     prec = KB.PREC_F64 if args.build_precision == "f64" else KB.PREC_F32
     grids = [(64, 16), (256, 16), (512, 16), (512, 32), (1024, 32)] if args.bins == "auto" else \

@@ -217,8 +217,10 @@ int32_t kf_smooth(kf_ctx* ctx, const kf_smooth_args* args);
  *               then the packed covariance (6), then 2 zero pads (48 bytes);
  *   layer_vmax [n_events * n_layers][2] float32 -- largest x-y eigenvalue
  *               and largest zz variance of the layer's hit covariances.
- * Workspace: kf_bin_hits_workspace_size(ldh) bytes of device memory owned
- * by the caller (per-hit bin ids). */
+ * Workspace: kf_bin_hits_workspace_size(ldh, n_events) bytes of device
+ * memory owned by the caller (per-hit bin ids, and the order in which the
+ * (event, layer) pairs are binned: largest first, which does not change the
+ * result). */
 #define KF_BINNED_FLOATS 12
 typedef struct {
   int64_t n_events;
@@ -235,7 +237,7 @@ typedef struct {
   size_t workspace_bytes;
   void* stream;
 } kf_bin_args;
-size_t kf_bin_hits_workspace_size(int64_t ldh);
+size_t kf_bin_hits_workspace_size(int64_t ldh, int64_t n_events);
 int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* args);
 
 /* ------------------------------------------------------------------------

@@ -49,13 +49,36 @@ __device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, d
   return ie * n_phi + ip;
 }
 
+// Launch order of the binning blocks: (event, layer) pairs by decreasing hit count (ties by index), so that
+// the largest pairs start first and the small ones fill in behind them (event sizes span a factor of 50; in
+// index order a large pair starting late holds the whole launch).  One block; the rank of each pair is counted
+// against every other pair, staged in LDS.  The result of the binning does not depend on the order.
+constexpr int kOrderMax = 8192;
+__global__ void __launch_bounds__(1024) el_order_kernel(int32_t n_el, const int64_t* __restrict__ layer_offsets,
+                                                        int32_t* __restrict__ el_order) {
+  __shared__ int32_t sz[kOrderMax];
+  for (int e = threadIdx.x; e < n_el; e += blockDim.x)
+    sz[e] = static_cast<int32_t>(layer_offsets[e + 1] - layer_offsets[e]);
+  __syncthreads();
+  for (int e = threadIdx.x; e < n_el; e += blockDim.x) {
+    const int32_t v = sz[e];
+    int rank = 0;
+    for (int f = 0; f < n_el; ++f) {
+      const int32_t w = sz[f];
+      rank += (w > v || (w == v && f < e)) ? 1 : 0;
+    }
+    el_order[rank] = e;
+  }
+}
+
 __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64_t* __restrict__ layer_offsets,
                                                           const float* __restrict__ hit_pos,
                                                           const float* __restrict__ hit_cov, int64_t ldh,
                                                           int32_t n_phi, int32_t n_eta, Geom g,
                                                           int32_t* __restrict__ bins, int32_t* __restrict__ bin_offsets,
                                                           int32_t* __restrict__ perm, float* __restrict__ binned,
-                                                          float* __restrict__ layer_vmax) {
+                                                          float* __restrict__ layer_vmax,
+                                                          const int32_t* __restrict__ el_order) {
   // per-wave bin counters [kBinWaves][nb] and bin totals [nb], sized by the launch (dynamic LDS) so that
   // a 64 x 16 binning takes 68 KB and two blocks share a compute unit
   extern __shared__ int32_t bin_lds[];
@@ -65,7 +88,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
 #define cnt(w, b) cnt_flat[(w) * nb_ + (b)]
   __shared__ int32_t wsum[kBinWaves];
   __shared__ uint32_t vmax_bits[2];
-  const int el = blockIdx.x;
+  const int el = el_order ? el_order[blockIdx.x] : static_cast<int>(blockIdx.x);
   const int l = el % L;
   const int nb = n_phi * n_eta;
   const int tid = threadIdx.x;
@@ -198,11 +221,12 @@ __global__ void __launch_bounds__(kBinThreads) bin_fine_kernel(int32_t L, const 
                                                                int32_t* __restrict__ bins,
                                                                int32_t* __restrict__ bin_offsets,
                                                                int32_t* __restrict__ perm, float* __restrict__ binned,
-                                                               float* __restrict__ layer_vmax) {
+                                                               float* __restrict__ layer_vmax,
+                                                               const int32_t* __restrict__ el_order) {
   extern __shared__ int32_t cnt_fine[];  // [nb] counts, then scatter cursors
   __shared__ int32_t wsum[kBinWaves];
   __shared__ uint32_t vmax_bits[2];
-  const int el = blockIdx.x;
+  const int el = el_order ? el_order[blockIdx.x] : static_cast<int>(blockIdx.x);
   const int l = el % L;
   const int nb = n_phi * n_eta;
   const int tid = threadIdx.x;
@@ -1185,7 +1209,11 @@ using kfh::set_error;
 
 extern "C" {
 
-size_t kf_bin_hits_workspace_size(int64_t ldh) { return static_cast<size_t>(ldh > 0 ? ldh : 0) * 4u; }
+// per-hit bin ids, then the launch order of the (event, layer) pairs (room for the largest layer count)
+static size_t bin_ids_bytes(int64_t ldh) { return (static_cast<size_t>(ldh > 0 ? ldh : 0) * 4u + 255) & ~size_t(255); }
+size_t kf_bin_hits_workspace_size(int64_t ldh, int64_t n_events) {
+  return bin_ids_bytes(ldh) + static_cast<size_t>(n_events > 0 ? n_events : 0) * KF_MAX_LAYERS * 4u;
+}
 
 int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
   if (int32_t rc = kfh::enter(ctx)) return rc;
@@ -1199,12 +1227,19 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
   if (!a->layer_offsets || !a->hit_pos || !a->hit_cov || !a->bin_offsets || !a->perm || !a->binned ||
       !a->layer_vmax)
     return set_error(KF_ERR_INVALID_ARG, "null array");
-  if (!a->workspace || a->workspace_bytes < kf_bin_hits_workspace_size(a->ldh))
-    return set_error(KF_ERR_WORKSPACE, "workspace of %zu bytes needed", kf_bin_hits_workspace_size(a->ldh));
+  if (!a->workspace || a->workspace_bytes < kf_bin_hits_workspace_size(a->ldh, a->n_events))
+    return set_error(KF_ERR_WORKSPACE, "workspace of %zu bytes needed", kf_bin_hits_workspace_size(a->ldh, a->n_events));
   const int L = ctx->geom.n_layers;
   const int64_t n_el = a->n_events * L;
   if (n_el > INT32_MAX) return set_error(KF_ERR_INVALID_ARG, "too many (event, layer) pairs");
   const int nb = a->n_phi * a->n_eta;
+  hipStream_t sm = kfh::stream_of(a->stream);
+  int32_t* el_order = nullptr;  // index order beyond kOrderMax pairs
+  if (n_el <= kOrderMax) {
+    el_order = reinterpret_cast<int32_t*>(static_cast<char*>(a->workspace) + bin_ids_bytes(a->ldh));
+    el_order_kernel<<<1, 1024, 0, sm>>>(static_cast<int32_t>(n_el), a->layer_offsets, el_order);
+    if (int32_t rc = kfh::check_hip(hipGetLastError(), "el_order_kernel launch")) return rc;
+  }
   if (nb <= kMaxBins) {
     const size_t lds_bytes = static_cast<size_t>(kBinWaves + 1) * nb * sizeof(int32_t);
     if (int32_t rc = kfh::check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(bin_kernel),
@@ -1212,9 +1247,9 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
                                                         static_cast<int>((kBinWaves + 1) * kMaxBins * sizeof(int32_t))),
                                     "hipFuncSetAttribute(bin_kernel)"))
       return rc;
-    bin_kernel<<<static_cast<unsigned>(n_el), kBinThreads, lds_bytes, kfh::stream_of(a->stream)>>>(
+    bin_kernel<<<static_cast<unsigned>(n_el), kBinThreads, lds_bytes, sm>>>(
         L, a->layer_offsets, a->hit_pos, a->hit_cov, a->ldh, a->n_phi, a->n_eta, ctx->dgeom,
-        static_cast<int32_t*>(a->workspace), a->bin_offsets, a->perm, a->binned, a->layer_vmax);
+        static_cast<int32_t*>(a->workspace), a->bin_offsets, a->perm, a->binned, a->layer_vmax, el_order);
     return kfh::check_hip(hipGetLastError(), "bin_kernel launch");
   }
   if (int32_t rc = kfh::check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(bin_fine_kernel),
@@ -1222,10 +1257,9 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
                                                       static_cast<int>(kMaxBinsFine * sizeof(int32_t))),
                                   "hipFuncSetAttribute(bin_fine_kernel)"))
     return rc;
-  bin_fine_kernel<<<static_cast<unsigned>(n_el), kBinThreads, static_cast<size_t>(nb) * sizeof(int32_t),
-                    kfh::stream_of(a->stream)>>>(
+  bin_fine_kernel<<<static_cast<unsigned>(n_el), kBinThreads, static_cast<size_t>(nb) * sizeof(int32_t), sm>>>(
       L, a->layer_offsets, a->hit_pos, a->hit_cov, a->ldh, a->n_phi, a->n_eta, ctx->dgeom,
-      static_cast<int32_t*>(a->workspace), a->bin_offsets, a->perm, a->binned, a->layer_vmax);
+      static_cast<int32_t*>(a->workspace), a->bin_offsets, a->perm, a->binned, a->layer_vmax, el_order);
   return kfh::check_hip(hipGetLastError(), "bin_fine_kernel launch");
 }
 

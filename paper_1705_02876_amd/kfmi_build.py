@@ -44,7 +44,7 @@ class kf_build_args(C.Structure):
 def declare(lib):
     P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
     lib.kf_bin_hits_workspace_size.restype = C.c_size_t
-    lib.kf_bin_hits_workspace_size.argtypes = [I64]
+    lib.kf_bin_hits_workspace_size.argtypes = [I64, I64]
     lib.kf_bin_hits.restype = I32
     lib.kf_bin_hits.argtypes = [P, P]
     lib.kf_build_workspace_size.restype = C.c_size_t
@@ -98,7 +98,7 @@ def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16,
                    perm=torch.empty(max(ldh, 1), dtype=torch.int32, device=dev),
                    binned=torch.empty(max(ldh, 1), BINNED_FLOATS, dtype=torch.float32, device=dev),
                    layer_vmax=torch.empty(n_events * L, 2, dtype=torch.float32, device=dev))
-    wsb = lib.kf_bin_hits_workspace_size(ldh)
+    wsb = lib.kf_bin_hits_workspace_size(ldh, n_events)
     if workspace is None:
         workspace = torch.empty(max(wsb, 4), dtype=torch.uint8, device=dev)
     a = kf_bin_args()

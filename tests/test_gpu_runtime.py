@@ -44,7 +44,8 @@ def test_graph_replays_bin_and_build(ctx, mode):
     prob = S.make_build_problem([1500, 2500, 7], det, 68)
     seeds, hits = KB.upload_problem(prob)
     ldh = hits["pos"].shape[1]
-    bws = torch.empty(max(kfmi.load_library().kf_bin_hits_workspace_size(ldh), 4), dtype=torch.uint8, device="cuda")
+    bws = torch.empty(max(kfmi.load_library().kf_bin_hits_workspace_size(ldh, prob.n_events), 4), dtype=torch.uint8,
+                      device="cuda")
     cfg = KB.make_cfg(mode=mode)
     wsb = torch.empty(KB.workspace_bytes(cfg, prob.n_events, seeds["n"]), dtype=torch.uint8, device="cuda")
     bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events, workspace=bws)
