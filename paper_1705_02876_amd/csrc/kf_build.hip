@@ -1111,8 +1111,32 @@ __global__ void __launch_bounds__(256) seed_count_kernel(int64_t n_seeds, int32_
   atomicAdd(&cells[static_cast<int64_t>(e) * kSeedCells + seed_cell(st, ld, s)], 1);
 }
 
-// one block per event: exclusive scan of its cell counts, offset by the event's first seed
-__global__ void __launch_bounds__(1024) seed_scan_kernel(const int64_t* __restrict__ seed_offsets,
+// Where each event's seeds start in the tile order: events with more seeds (denser events, whose tiles cost
+// more) first, ties by index, so that the expensive tiles start early and the cheap ones fill in behind them.
+// One block; beyond kOrderMax events the events keep index order.
+__global__ void __launch_bounds__(1024) event_base_kernel(int32_t n_events, const int64_t* __restrict__ seed_offsets,
+                                                          int64_t* __restrict__ base) {
+  __shared__ int32_t cnt[kOrderMax];
+  if (n_events > kOrderMax) {
+    for (int e = threadIdx.x; e < n_events; e += blockDim.x) base[e] = seed_offsets[e];
+    return;
+  }
+  for (int e = threadIdx.x; e < n_events; e += blockDim.x)
+    cnt[e] = static_cast<int32_t>(seed_offsets[e + 1] - seed_offsets[e]);
+  __syncthreads();
+  for (int e = threadIdx.x; e < n_events; e += blockDim.x) {
+    const int32_t v = cnt[e];
+    int64_t b = seed_offsets[0];
+    for (int f = 0; f < n_events; ++f) {
+      const int32_t w = cnt[f];
+      b += (w > v || (w == v && f < e)) ? w : 0;
+    }
+    base[e] = b;
+  }
+}
+
+// one block per event: exclusive scan of its cell counts, offset by where the event's seeds start
+__global__ void __launch_bounds__(1024) seed_scan_kernel(const int64_t* __restrict__ base,
                                                          int32_t* __restrict__ cells) {
   __shared__ int32_t part[1024];
   const int e = blockIdx.x;
@@ -1134,7 +1158,7 @@ __global__ void __launch_bounds__(1024) seed_scan_kernel(const int64_t* __restri
     part[t] += y;
     __syncthreads();
   }
-  int32_t run = static_cast<int32_t>(seed_offsets[e]) + part[t] - sum;
+  int32_t run = static_cast<int32_t>(base[e]) + part[t] - sum;
 #pragma unroll
   for (int k = 0; k < per; ++k) {
     c[t * per + k] = run;
@@ -1272,7 +1296,8 @@ size_t cells_bytes(int64_t n_events) { return align256(static_cast<size_t>(n_eve
 size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_events, int64_t n_seeds) {
   if (!cfg || n_events < 0 || n_seeds < 0) return 0;
   size_t b = kQueueBytes;  // persistent work queue (kept in every layout)
-  if (cfg->seed_order) b += cells_bytes(n_events) + align256(static_cast<size_t>(n_seeds) * 4);
+  if (cfg->seed_order)
+    b += cells_bytes(n_events) + align256(static_cast<size_t>(n_seeds) * 4) + align256(static_cast<size_t>(n_events) * 8);
   return (cfg->mode == KF_BUILD_PERSISTENT || cfg->seed_order) ? b : 0;
 }
 
@@ -1361,7 +1386,10 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
     fill_i32_kernel<<<kfh::grid_for(nc, 256), 256, 0, stream>>>(cells, nc, 0);
     seed_count_kernel<<<kfh::grid_for(a->n_seeds, 256), 256, 0, stream>>>(
         a->n_seeds, static_cast<int32_t>(a->n_events), a->seed_offsets, a->seed_state, a->ld_seed, cells);
-    seed_scan_kernel<<<static_cast<unsigned>(a->n_events), 1024, 0, stream>>>(a->seed_offsets, cells);
+    int64_t* base = reinterpret_cast<int64_t*>(w + kQueueBytes + cells_bytes(a->n_events) +
+                                               align256(static_cast<size_t>(a->n_seeds) * 4));
+    event_base_kernel<<<1, 1024, 0, stream>>>(static_cast<int32_t>(a->n_events), a->seed_offsets, base);
+    seed_scan_kernel<<<static_cast<unsigned>(a->n_events), 1024, 0, stream>>>(base, cells);
     seed_scatter_kernel<<<kfh::grid_for(a->n_seeds, 256), 256, 0, stream>>>(
         a->n_seeds, static_cast<int32_t>(a->n_events), a->seed_offsets, a->seed_state, a->ld_seed, cells, order);
     if (int32_t rc = kfh::check_hip(hipGetLastError(), "seed ordering launch")) return rc;
