@@ -387,13 +387,18 @@ __device__ __forceinline__ void smooth_bwd_body(I n, I ld, const int8_t* __restr
   if (last < 1) return;
   const int8_t qi = *elem(charge, i);
   const T a = T(-static_cast<double>(qi) * kCLight * g.bz);
+  // The carried state (xs, cs) is the smoothed state of the layer outside the current one.  A lane that takes
+  // no step at a layer (above its last hit layer, at the last hit layer itself, or after a failed step) takes
+  // that layer's row as read, so at its last hit layer it picks up the filtered (= smoothed) state there.
+  // Every lane writes every row at that row's iteration, in one store instruction, so the cache lines of a row
+  // are written whole (lanes that skipped their store left partial lines, which the cache filled from memory
+  // first).  The next row inward is fetched while the current step computes (one wave per SIMD leaves nothing
+  // else to cover the latency); rows of every layer exist (NaN above the last hit layer).
   float xs[6], cs[21];
-  load_row(state_out, cov_out, ld, last, i, xs, cs);
-  // The filtered row of the next layer inward is fetched while this layer's step computes (one wave per SIMD
-  // leaves nothing else to cover the latency).  Every lane fetches at every layer index, also where it has
-  // no step (rows of every layer exist: NaN above the last hit layer), so the fetch needs no branch.
+  load_row(state_out, cov_out, ld, L - 1, i, xs, cs);
   float xn[6], cn[21];
   load_row(state_out, cov_out, ld, L - 2, i, xn, cn);
+  bool live = true;
   for (int l = L - 2; l >= 0; --l) {
     float xf[6], cf[21];
 #pragma unroll
@@ -401,11 +406,21 @@ __device__ __forceinline__ void smooth_bwd_body(I n, I ld, const int8_t* __restr
 #pragma unroll
     for (int k = 0; k < 21; ++k) cf[k] = cn[k];
     if (l >= 1) load_row(state_out, cov_out, ld, l - 1, i, xn, cn);
-    if (l >= last) continue;
-    const int32_t st = rts_step<T, double>(xf, cf, a, g, l, xs, cs);
-    if (st) {
-      *elem(status_out, i) = st;
-      return;
+    bool stepped = false;
+    if (live && l < last) {
+      const int32_t st = rts_step<T, double>(xf, cf, a, g, l, xs, cs);
+      if (st) {
+        *elem(status_out, i) = st;
+        live = false;
+      } else {
+        stepped = true;
+      }
+    }
+    if (!stepped) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) xs[k] = xf[k];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) cs[k] = cf[k];
     }
     store_row(state_out, cov_out, ld, l, i, xs, cs);
   }
