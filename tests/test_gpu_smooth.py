@@ -187,3 +187,17 @@ def test_smooth_full_size_sampled(ctx, orc):
     ok = same & (ost == 0)
     _compare_rows(gs, gc, os_, oc, ok, min_cos_psi(sub) < GRAZING_COS, "full-size smooth")
     assert (gst == 0).mean() > 0.999
+
+
+@pytest.mark.parametrize("n_layers", [1, 2])
+def test_smooth_few_layers(ctx, orc, n_layers):
+    """One layer: the only row is the filtered state (no backward step).  Two layers: one backward step."""
+    det = dataclasses.replace(S.detector_full(), radii=tuple(S.detector_full().radii[:n_layers]))
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    fp = S.make_fit_problem(300, det, 900 + n_layers, p_miss=0.0, min_hits=n_layers)
+    gs, gc, gst, gchi, gnh = _smooth_gpu(ctx, fp)
+    os_, oc, ost = _oracle_smooth(orc, det32, fp)
+    ok = (gst == 0) & (ost == 0)
+    assert ok.mean() > 0.99
+    _compare_rows(gs, gc, os_, oc, ok, min_cos_psi(fp) < GRAZING_COS, f"smooth {n_layers} layers")
