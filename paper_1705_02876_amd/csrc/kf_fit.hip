@@ -392,8 +392,8 @@ __device__ __forceinline__ void smooth_bwd_body(I n, I ld, const int8_t* __restr
   // that layer's row as read, so at its last hit layer it picks up the filtered (= smoothed) state there.
   // Every lane writes every row at that row's iteration, in one store instruction, so the cache lines of a row
   // are written whole (lanes that skipped their store left partial lines, which the cache filled from memory
-  // first).  The next row inward is fetched while the current step computes (one wave per SIMD leaves nothing
-  // else to cover the latency); rows of every layer exist (NaN above the last hit layer).
+  // first).  The next row inward is fetched while the current step computes (two waves per SIMD cover little
+  // of the latency); rows of every layer exist (NaN above the last hit layer).
   float xs[6], cs[21];
   load_row(state_out, cov_out, ld, L - 1, i, xs, cs);
   float xn[6], cn[21];
