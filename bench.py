@@ -223,10 +223,11 @@ def smooth_leg(ctx, fp, t, L, reps=3, fp64=False):
     flop = fit_flops(fp) + FLOP_PER_SMOOTH_STEP * steps
     byt = smooth_bytes(n, L, int((fp.hit_idx >= 0).sum()))
     sec = ms * 1e-3
+    tf, tb = measured_traffic("smooth_fwd_kernel"), measured_traffic("smooth_bwd_kernel")
     res = {"kernels": "smooth_fwd_kernel + smooth_bwd_kernel", "avg_ms": ms, "tracks_per_s": n / sec, "backward_steps": steps,
            "flop": flop, "tflops": flop / sec / 1e12, "alu_frac": flop / sec / 1e12 / VALU_PEAK_TFLOPS,
            "bytes": byt, "gbs": byt / sec / 1e9, "hbm_frac": byt / sec / 1e9 / HBM_PEAK_GBS,
-           "status_nonzero": int((~ok).sum()),
+           "traffic": (tf + tb) if tf is not None and tb is not None else None, "status_nonzero": int((~ok).sum()),
            "note": "the bytes are the algorithmic ones (inputs once, every layer's row out once); the kernel also "
                    "writes each filtered row and reads it back for the backward pass"}
     del rows_s, rows_c
