@@ -307,3 +307,22 @@ def test_learned_window_parity(ctx, orc, N, mode, precision):
           f"{gpu['counters'][5]}, window-stable seeds {(ora['margin_window'] > WSTABLE).mean():.3f}", flush=True)
     assert ora["fallbacks"].sum() > 0
     _compare(gpu, ora, label=f"learned N={N} mode={mode} precision={precision}", min_same=0.9)
+
+
+@pytest.mark.parametrize("n_events", [500, 8300])
+def test_many_small_events(ctx, orc, n_events):
+    """Beyond 8192 (event, layer) pairs (500 events) the binning blocks, and beyond 8192 events (8300) the
+    build's events, keep index order instead of largest first: binning bit for bit and candidates as the
+    oracle's."""
+    det = S.detector_full()
+    det32 = det.as_float32()
+    rng = np.random.default_rng(n_events)
+    prob = S.make_build_problem([int(x) for x in rng.integers(0, 4, n_events)], det, 83)
+    print(f"[many events] {n_events} events, {prob.seed_state.shape[0]} seeds", flush=True)
+    gpu, bins = _gpu_build(ctx, prob, N=6, mode=0, det32=det32, precision=0)
+    if n_events * det.n_layers * 1025 * 4 < (1 << 28):  # compare the bins where their offset table stays small
+        bo, perm, _ = orc.bin_hits(orc.geometry(det32), prob.n_events, prob.layer_hit_offsets, rounded(prob.hit_pos))
+        assert np.array_equal(bins["bin_offsets"].cpu().numpy(), bo)
+        assert np.array_equal(bins["perm"].cpu().numpy()[: perm.size].astype(np.int64), perm)
+    ora = _oracle_build(orc, prob, det32, N=6)
+    _compare(gpu, ora, label=f"{n_events} small events")
