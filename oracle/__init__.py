@@ -42,6 +42,9 @@ class BuildCfg(C.Structure):
         ("window_margin", C.c_double),
         ("mlp_params", C.c_void_p),
         ("learned_nsigma", C.c_double),
+        ("bin_offsets", C.c_void_p),
+        ("perm", C.c_void_p),
+        ("layer_vmax", C.c_void_p),
     ]
 
 
@@ -81,6 +84,8 @@ def _declare(L):
     L.or_rts_step.argtypes = [P] * 10
     L.or_rts_step.restype = None
     L.or_bin_hits.argtypes = [P, C.c_int64, P, P, C.c_int32, C.c_int32, P, P, P]
+    L.or_layer_vmax.restype = None
+    L.or_layer_vmax.argtypes = [P, C.c_int64, P, P, P]
     L.or_build.restype = C.c_int32
     L.or_build.argtypes = [P, P, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, C.c_int32] + [P] * 12
     L.or_bf16.restype = C.c_double
@@ -244,17 +249,35 @@ def bin_hits(g, n_events, layer_offsets, hit_pos, n_phi=64, n_eta=16):
     return bo.reshape(n_events * L, nb + 1), perm[:H], bin_of[:H]
 
 
+def layer_vmax(g, n_events, layer_offsets, hit_cov_full):
+    """Per (event, layer): largest x-y eigenvalue and largest zz entry of the hit covariances, (E*L, 2)."""
+    lo = np.ascontiguousarray(layer_offsets, dtype=np.int64)
+    hc = _f64(hit_cov_full)
+    out = np.zeros((n_events * g.n_layers, 2))
+    lib().or_layer_vmax(C.byref(g), int(n_events), _p(lo), _p(hc), _p(out))
+    return out
+
+
 def build(g, prob, max_cands=6, mode=1, chi2_cut=30.0, n_phi=64, n_eta=16, window_margin=0.01, seeds=None,
-          hit_pos=None, hit_cov_full=None, seed_state=None, seed_cov=None, mlp_params=None, learned_nsigma=4.0):
+          hit_pos=None, hit_cov_full=None, seed_state=None, seed_cov=None, mlp_params=None, learned_nsigma=4.0,
+          prebinned=None):
     """Run the oracle builder on a synth.BuildProblem (optionally a subset of seeds).
     mlp_params (4866 float64, or None for the plain window) selects the learned window.
+    prebinned: optional (bin_offsets, perm, layer_vmax) from bin_hits and layer_vmax on the same hits and
+    grid, so that several calls over one set of events bin it once.
 
     Returns dict of numpy arrays (see kf_oracle.h)."""
     mp = None if mlp_params is None else _f64(mlp_params)
     if mp is not None and mp.size != 4866:
         raise ValueError("mlp_params must hold 4866 values")
+    pb = [None, None, None]
+    if prebinned is not None:
+        bo, pm, vm = prebinned
+        pb = [np.ascontiguousarray(bo, dtype=np.int32), np.ascontiguousarray(pm, dtype=np.int64), _f64(vm)]
+        if pb[0].size != prob.n_events * g.n_layers * (n_phi * n_eta + 1) or pb[2].size != 2 * prob.n_events * g.n_layers:
+            raise ValueError("prebinned arrays do not fit this problem and grid")
     cfg = BuildCfg(max_cands, mode, chi2_cut, n_phi, n_eta, window_margin, None if mp is None else mp.ctypes.data,
-                   learned_nsigma)
+                   learned_nsigma, *[None if a is None else a.ctypes.data for a in pb])
     L = g.n_layers
     E = prob.n_events
     hp = _f64(prob.hit_pos if hit_pos is None else hit_pos)

@@ -668,6 +668,22 @@ int32_t or_bin_hits(const or_geometry* g, int64_t n_events, const int64_t* layer
   return 0;
 }
 
+void or_layer_vmax(const or_geometry* g, int64_t n_events, const int64_t* layer_offsets, const double* hit_cov,
+                   double* vmax) {
+  const int64_t n_el = n_events * g->n_layers;
+  for (int64_t el = 0; el < n_el; ++el) {
+    vmax[2 * el] = 0.0;
+    vmax[2 * el + 1] = 0.0;
+    for (int64_t h = layer_offsets[el]; h < layer_offsets[el + 1]; ++h) {
+      const double* V = hit_cov + 9 * h;
+      double a = V[0], b = V[1], c = V[4];
+      double lam = 0.5 * (a + c) + sqrt(0.25 * (a - c) * (a - c) + b * b);
+      if (lam > vmax[2 * el]) vmax[2 * el] = lam;
+      if (V[8] > vmax[2 * el + 1]) vmax[2 * el + 1] = V[8];
+    }
+  }
+}
+
 /* ------------------------------------------------------------------------
  * Combinatorial building.
  * ---------------------------------------------------------------------- */
@@ -821,24 +837,25 @@ int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events
   if (N < 1 || first_layer < 0 || n_seeds < 0) return -1;
   const double cut = cfg->chi2_cut;
   const int nphi = cfg->n_phi, neta = cfg->n_eta, nb = nphi * neta;
-  int32_t* bin_offsets = NULL;
-  int64_t* perm = NULL;
-  double* vmax = NULL; /* per (event, layer): max x-y eigenvalue and max zz of the hit covariances */
+  int32_t* own_bins = NULL;
+  int64_t* own_perm = NULL;
+  double* own_vmax = NULL;
+  const int32_t* bin_offsets = cfg->bin_offsets;
+  const int64_t* perm = cfg->perm;
+  const double* vmax = cfg->layer_vmax; /* per (event, layer): max x-y eigenvalue and max zz of the hit covariances */
   int64_t H = layer_offsets[n_events * L];
-  if (cfg->mode == 1) {
-    bin_offsets = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_events * L) * (nb + 1));
-    perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)(H > 0 ? H : 1));
-    or_bin_hits(g, n_events, layer_offsets, hit_pos, nphi, neta, bin_offsets, perm, NULL);
+  if (cfg->mode == 1 && (!bin_offsets || !perm)) {
+    own_bins = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_events * L) * (nb + 1));
+    own_perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)(H > 0 ? H : 1));
+    or_bin_hits(g, n_events, layer_offsets, hit_pos, nphi, neta, own_bins, own_perm, NULL);
+    bin_offsets = own_bins;
+    perm = own_perm;
   }
-  vmax = (double*)calloc((size_t)(n_events * L) * 2, sizeof(double));
-  for (int64_t el = 0; el < n_events * L; ++el)
-    for (int64_t h = layer_offsets[el]; h < layer_offsets[el + 1]; ++h) {
-      const double* V = hit_cov + 9 * h;
-      double a = V[0], b = V[1], c = V[4];
-      double lam = 0.5 * (a + c) + sqrt(0.25 * (a - c) * (a - c) + b * b);
-      if (lam > vmax[2 * el]) vmax[2 * el] = lam;
-      if (V[8] > vmax[2 * el + 1]) vmax[2 * el + 1] = V[8];
-    }
+  if (!vmax) {
+    own_vmax = (double*)malloc(sizeof(double) * (size_t)(n_events * L) * 2);
+    or_layer_vmax(g, n_events, layer_offsets, hit_cov, own_vmax);
+    vmax = own_vmax;
+  }
 
   ocand* cur = (ocand*)calloc((size_t)N, sizeof(ocand));
   ocand* nxt = (ocand*)calloc((size_t)N, sizeof(ocand));
@@ -1054,8 +1071,8 @@ int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events
   free(nxt);
   free(prop);
   free(cv.v);
-  free(bin_offsets);
-  free(perm);
-  free(vmax);
+  free(own_bins);
+  free(own_perm);
+  free(own_vmax);
   return 0;
 }

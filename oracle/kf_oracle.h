@@ -125,7 +125,20 @@ typedef struct {
    * its prediction; when no hit does, the plain definition applies. */
   const double* mlp_params;
   double learned_nsigma;
+  /* optional, for callers that build one set of events in several calls
+   * (NULL = computed inside from the hits): the binned mode's bin offsets and
+   * permutation as or_bin_hits gives them for this cfg's grid, and per
+   * (event, layer) the largest x-y eigenvalue and largest zz entry of the hit
+   * covariances, as or_layer_vmax gives them */
+  const int32_t* bin_offsets;
+  const int64_t* perm;
+  const double* layer_vmax;
 } or_build_cfg;
+
+/* Per (event, layer): the largest eigenvalue of the x-y block and the largest
+ * zz entry of its hits' covariances (full 3x3, row-major), into vmax[2 E L]. */
+void or_layer_vmax(const or_geometry* g, int64_t n_events, const int64_t* layer_offsets, const double* hit_cov,
+                   double* vmax);
 
 int32_t or_build(const or_geometry* g, const or_build_cfg* cfg, int64_t n_events, const int64_t* layer_offsets,
                  const double* hit_pos, const double* hit_cov, int64_t n_seeds, const int64_t* seed_event,

@@ -1,8 +1,9 @@
 """Physics judge of track building: efficiency and fake rate (host side, untimed).
 
-Paper, Sec. 3.2: a candidate matching fewer than 7 hits of a simulated track
-counts as neither a success nor a fake.  The fraction of a candidate's hits
-that must come from the matched track is not stated; 75% is used here.
+Sec. 3.2 scores a candidate only when one simulated track supplies at least
+seven of its hits; a candidate short of that is left out of both the
+efficiency and the fake count.  The share of the candidate's hits that must
+come from the matched track is not given there; 75% is used here.
 """
 from __future__ import annotations
 

@@ -72,14 +72,22 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
-def check_offsets(t, count, limit, name):
-    """Host check of a device offset array: `count` + 1 ascending int64 values in [0, limit]."""
+# The build's rank key and back-pointer records carry a hit's index within its (event, layer) in 24 bits, with
+# 2^24 - 1 reserved for "no hit": an (event, layer) may hold at most 2^24 - 2 hits.
+MAX_LAYER_HITS = (1 << 24) - 2
+
+
+def check_offsets(t, count, limit, name, max_run=None):
+    """Host check of a device offset array: `count` + 1 ascending int64 values in [0, limit], and consecutive
+    differences at most `max_run` when given."""
     import torch
     if t.dtype != torch.int64 or t.numel() < count + 1:
         raise ValueError(f"{name}: need {count + 1} int64 offsets")
     h = t[: count + 1].cpu()
     if int(h[0]) < 0 or int(h[-1]) > limit or bool((h[1:] < h[:-1]).any()):
         raise ValueError(f"{name}: offsets must ascend within [0, {limit}]")
+    if max_run is not None and count > 0 and int((h[1:] - h[:-1]).max()) > max_run:
+        raise ValueError(f"{name}: a range holds more than {max_run} entries")
 
 
 def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16, out=None, workspace=None,
@@ -92,7 +100,7 @@ def bin_hits(ctx, layer_offsets, hit_pos, hit_cov, n_events, n_phi=64, n_eta=16,
     L = ctx.n_layers
     dev = hit_pos.device
     if check:
-        check_offsets(layer_offsets, n_events * L, ldh, "layer_offsets")
+        check_offsets(layer_offsets, n_events * L, ldh, "layer_offsets", max_run=MAX_LAYER_HITS)
     if out is None:
         out = dict(bin_offsets=torch.empty(n_events * L, n_phi * n_eta + 1, dtype=torch.int32, device=dev),
                    perm=torch.empty(max(ldh, 1), dtype=torch.int32, device=dev),
@@ -157,7 +165,8 @@ def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=Non
         check_offsets(seeds["offsets"], n_events, S, "seed_offsets")
         if int(seeds["offsets"][n_events].item()) != S or int(seeds["offsets"][0].item()) != 0:
             raise ValueError("seed_offsets must start at 0 and end at n_seeds")
-        check_offsets(layer_offsets, n_events * L, bins["binned"].shape[0], "layer_offsets")
+        check_offsets(layer_offsets, n_events * L, bins["binned"].shape[0], "layer_offsets",
+                      max_run=MAX_LAYER_HITS)
     if out is None:
         out = dict(n_cands=torch.empty(max(S, 1), dtype=torch.int32, device=dev),
                    cand_hits=torch.empty(L, max(S, 1), N, dtype=torch.int32, device=dev),

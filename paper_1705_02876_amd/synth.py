@@ -4,16 +4,20 @@ This module produces the inputs that both the GPU library and the FP64 oracle
 consume: charged-particle tracks in a uniform solenoidal field crossing equally
 spaced, fixed-length concentric cylinders, with Gaussian hit smearing, optional
 multiple scattering and mean energy loss, random missing hits, uniform noise
-hits, and seeds derived from the first three hits of each simulated track.
+hits, and one seed per simulated track carrying its hits on the first three
+layers.
 
-The paper's workload (Sec. 3.2): seeds from the first three hits of every
-simulated track, a simplified detector of equally spaced fixed-length
-concentric cylinders, and in-house simulation with Gaussian smearing of the
-hit positions.  Nothing here runs the Kalman filter: the truth trajectory is
-stepped with the exact circle/circle intersection of the track's transverse
-circle with each layer.  Seed covariances come from the helix through the
-vertex fitted to the first three hits (finite-difference error propagation of
-the hit errors), seed means are drawn around the truth at the third hit.
+Sec. 3.2 describes the workload this stands in for: a detector of equally
+spaced concentric cylinders of fixed length, an in-house simulation that
+smears hit positions with Gaussians, and one seed per simulated track made
+from its first three hits.  Nothing here runs the Kalman filter: the truth
+trajectory is stepped with the exact circle/circle intersection of the
+track's transverse circle with each layer.  A seed carries its three hits;
+its covariance is that of the helix through the vertex and those hits
+(finite-difference error propagation of the hit errors), and its state is
+drawn around the truth at the third hit from that covariance
+(`seed_mode="truth"`, the default), or is the state of a three-hit circle
+and helix fit itself (`seed_mode="hits"`, see `seeds_from_hits`).
 
 All arithmetic is float64; callers cast to float32 for the GPU and pass the
 float32-rounded values back to the oracle so both sides see identical inputs.
@@ -551,13 +555,18 @@ class BuildProblem:
 
 
 def make_build_problem(track_counts, det: Detector, seed, p_miss=0.05, noise_frac=0.2, smear=True,
-                       pt_range=(0.5, 10.0), eta_range=(-1.0, 1.0), seed_draw=True):
+                       pt_range=(0.5, 10.0), eta_range=(-1.0, 1.0), seed_draw=True, seed_mode="truth"):
     """Events of sim tracks plus `noise_frac * n_tracks` uniform noise hits per layer.
 
     The first three layers always carry the track's hit; one seed per track.
     Hits inside each (event, layer) are randomly permuted (read-out order is
-    unrelated to the track order).
+    unrelated to the track order).  seed_mode "truth": the seed state is drawn
+    around the truth at the third hit (truth_seeds); "hits": it is the helix
+    through the vertex and the three smeared hits, with that fit's covariance
+    (seeds_from_hits), the charge from the turning sense.
     """
+    if seed_mode not in ("truth", "hits"):
+        raise ValueError(f"unknown seed_mode {seed_mode!r}")
     rng = np.random.Generator(np.random.PCG64(seed))
     L = det.n_layers
     E = len(track_counts)
@@ -594,7 +603,10 @@ def make_build_problem(track_counts, det: Detector, seed, p_miss=0.05, noise_fra
             trk_chunks.append(alltrk)
             offs.append(base + allpos.shape[0])
         # seeds: one per track, covariance from its layer 0..2 hits, mean drawn around the truth
-        st, C, q = truth_seeds(rng, sim, det, draw=seed_draw)
+        if seed_mode == "truth":
+            st, C, q = truth_seeds(rng, sim, det, draw=seed_draw)
+        else:
+            st, C, q = seeds_from_hits(sim["hit_pos"][0:3], det)
         seed_state.append(st)
         seed_cov.append(C)
         seed_q.append(q)

@@ -269,3 +269,79 @@ def test_residual_emission(ctx, orc):
     assert np.array_equal(finite, has)
     # targets: tangential offsets are O(prediction sigma), z offsets too
     assert np.nanstd(rows[8]) < 0.5 and np.nanstd(rows[9]) < 2.0
+
+
+def test_fit_and_smoother_64bit_addressing(ctx, orc):
+    """Arrays whose extent crosses 2^30 elements take the 64-bit addressing kernels (fit_kernel_i64,
+    smooth_fwd_kernel_i64, smooth_bwd_kernel_i64): a covariance array with ld = 51.2 M columns for the fit
+    (21 ld > 2^30, rows past 4 GiB) and smoothed rows with ld = 3.1 M for the smoother (17 * 21 ld > 2^30).
+    Only the first n columns hold tracks.  The results equal the 32-bit kernels' bit for bit and the
+    oracle's at the usual tolerances."""
+    import torch
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    L = det.n_layers
+    n = 3000
+    fp = S.make_fit_problem(n, det, 4097, p_miss=0.05, min_hits=6)
+    base = fit_inputs_gpu(fp)
+    os_, oc, ochi, onh, ost = oracle_fit_on_f32(orc, det32, fp)
+
+    def wide(t, ld):
+        w = torch.empty(t.shape[0], ld, dtype=t.dtype, device="cuda")
+        w[:, :n] = t[:, :n]
+        return w
+
+    # fit: narrow (ld = n) and wide (ld = 51.2 M) launches on the same tracks
+    ldw = 51_200_000
+    assert 21 * ldw > (1 << 30) and 21 * n < (1 << 30)
+    outs = []
+    for ld in (n, ldw):
+        print(f"[64-bit addressing] fit, ld = {ld}", flush=True)
+        st_in, cv_in = (base["state"], base["cov"]) if ld == n else (wide(base["state"], ld), wide(base["cov"], ld))
+        so = torch.empty(6, ld, dtype=torch.float32, device="cuda")
+        co = torch.empty(21, ld, dtype=torch.float32, device="cuda")
+        chi2 = torch.empty(n, dtype=torch.float32, device="cuda")
+        nh = torch.empty(n, dtype=torch.int32, device="cuda")
+        st = torch.empty(n, dtype=torch.int32, device="cuda")
+        ctx.kf_fit(st_in, cv_in, base["q"], base["hidx"], base["hpos"], base["hcov"], so, co, chi2, nh, st, n=n)
+        torch.cuda.synchronize()
+        outs.append((so[:, :n].cpu().numpy(), co[:, :n].cpu().numpy(), chi2.cpu().numpy(), nh.cpu().numpy(),
+                     st.cpu().numpy()))
+        del st_in, cv_in, so, co
+        torch.cuda.empty_cache()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b, equal_nan=True)
+    gs, gc = outs[1][0].T.astype(np.float64), S.unpack6(outs[1][1].T.astype(np.float64))
+    gst = outs[1][4]
+    ok = (gst == 0) & (ost == 0)
+    assert ok.mean() > 0.995
+    check_params(gs[ok], os_[ok], "wide fit state")
+    check_chi2(outs[1][2][ok].astype(np.float64), ochi[ok], "wide fit chi2")
+    graz = min_cos_psi(fp) < GRAZING_COS
+    check_cov(gc[ok & ~graz], oc[ok & ~graz], "wide fit cov")
+
+    # smoother: rows (L, 21, ld) with ld = 3.1 M cross 2^30 elements
+    lds = 3_100_000
+    assert L * 21 * lds > (1 << 30) and L * 21 * n < (1 << 30)
+    rows = []
+    for ld in (n, lds):
+        print(f"[64-bit addressing] smoother, ld = {ld}", flush=True)
+        st_in, cv_in = (base["state"], base["cov"]) if ld == n else (wide(base["state"], ld), wide(base["cov"], ld))
+        rs = torch.empty(L, 6, ld, dtype=torch.float32, device="cuda")
+        rc = torch.empty(L, 21, ld, dtype=torch.float32, device="cuda")
+        st = torch.empty(n, dtype=torch.int32, device="cuda")
+        ctx.kf_smooth(st_in, cv_in, base["q"], base["hidx"], base["hpos"], base["hcov"], rs, rc, st, n=n)
+        torch.cuda.synchronize()
+        rows.append((rs[:, :, :n].cpu().numpy(), rc[:, :, :n].cpu().numpy(), st.cpu().numpy()))
+        del st_in, cv_in, rs, rc
+        torch.cuda.empty_cache()
+    for a, b in zip(rows[0], rows[1]):
+        assert np.array_equal(a, b, equal_nan=True)
+    oss, osc, osst = orc.smooth(orc.geometry(det32), rounded(fp.state0), rounded(S.unpack6(S.pack6(fp.cov0))),
+                                fp.q, fp.hit_idx, rounded(fp.hit_pos), S.unpack3(rounded(fp.hit_cov)))
+    gss = rows[1][0].transpose(2, 0, 1).astype(np.float64)
+    okk = (rows[1][2] == 0) & (osst == 0)
+    fin = np.isfinite(oss[..., 0]) & okk[:, None]
+    assert np.array_equal(fin, np.isfinite(gss[..., 0]) & okk[:, None])
+    check_params(gss[fin], oss[fin], "wide smoothed state")

@@ -206,3 +206,19 @@ def test_combinatorial_not_worse_than_best_hit(orc):
     r6 = judge.judge_problem(prob, orc.build(g, prob, max_cands=6)["cand_hits"][:, 0, :])
     assert r6["eff"] >= r1["eff"]
     assert r6["eff"] > 0.9
+
+
+def test_prebinned_build_equals_internal_binning(orc):
+    """The oracle builder given the bins and layer maxima computed once (bin_hits, layer_vmax) gives the same
+    candidates as when it bins inside each call, for any split of the seeds over calls."""
+    det = S.detector_full()
+    g = orc.geometry(det)
+    prob = S.make_build_problem([300, 0, 450], det, 91)
+    hc = orc.full3(prob.hit_cov)
+    ref = orc.build(g, prob, max_cands=4, hit_cov_full=hc)
+    bo, perm, _ = orc.bin_hits(g, prob.n_events, prob.layer_hit_offsets, prob.hit_pos)
+    vm = orc.layer_vmax(g, prob.n_events, prob.layer_hit_offsets, hc)
+    parts = np.array_split(np.arange(prob.seed_state.shape[0]), 3)
+    outs = [orc.build(g, prob, max_cands=4, hit_cov_full=hc, seeds=ix, prebinned=(bo, perm, vm)) for ix in parts]
+    for k in ("n_cands", "cand_hits", "cand_chi2", "cand_nhits", "cand_status", "best_state"):
+        assert np.array_equal(np.concatenate([o[k] for o in outs]), ref[k]), k

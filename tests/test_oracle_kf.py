@@ -257,3 +257,55 @@ def test_update_is_accurate_for_an_ill_conditioned_residual_covariance(orc):
     assert np.all(np.abs(co - C_ex) <= 1e-6 * np.outer(d, d) + 1e-18)
     assert np.abs(so - s_ex).max() < 1e-10
     assert abs(c2 - chi2_ex) < 1e-8 * max(chi2_ex, 1.0)
+
+
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
+        return json.load(fh)
+
+
+def test_highland_width_matches_pdg_golden(orc):
+    """The scattering term of the oracle's material step against Highland widths worked out by hand from the
+    PDG formula (tests/golden/material.json): no energy loss, so the momentum block gains p^2 theta0^2 in the
+    directions perpendicular to the momentum.  The 60-degree case checks the path thickness x/X0 / cos(psi)."""
+    gold = _golden("material.json")
+    for c in gold["highland"]:
+        oblique = abs(c["x_over_x0"] - 0.04) < 1e-12 and c["p"] == 2.0
+        xx0 = 0.02 if oblique else c["x_over_x0"]
+        det = S.Detector(radii=(10.0,), x_over_x0=xx0, eloss_per_x0=0.0, mass=c["mass"])
+        g = orc.geometry(det)
+        ang = np.pi / 3 if oblique else 0.0  # angle between the momentum and the layer normal (x axis)
+        p = c["p"]
+        s = np.array([10.0, 0.0, 0.0, p * np.cos(ang), p * np.sin(ang), 0.0])
+        st, s2, C2 = orc.material_one(g, 0, s, np.zeros((6, 6)))
+        assert st == 0
+        assert np.allclose(s2, s, rtol=0, atol=0)  # no loss: momentum unchanged
+        theta0 = np.sqrt(C2[5, 5]) / p  # z is perpendicular to the momentum in every case
+        assert abs(theta0 - c["theta0"]) <= 1e-10 * c["theta0"], (c, theta0)
+        # the other perpendicular direction carries the same variance, the momentum direction none
+        u = s[3:] / p
+        e1 = np.array([-u[1], u[0], 0.0])
+        assert abs(e1 @ C2[3:, 3:] @ e1 - C2[5, 5]) <= 1e-12 * C2[5, 5]
+        assert abs(u @ C2[3:, 3:] @ u) <= 1e-12 * C2[5, 5]
+
+
+def test_mean_energy_loss_matches_pdg_silicon(orc):
+    """The detector's mean loss per radiation length is the minimum-ionising loss of silicon from the PDG
+    tables (1.664 MeV cm^2/g times X0 = 21.82 g/cm^2, tests/golden/material.json), and one 0.02 X0 layer
+    crossed at normal incidence removes 0.02 of it from the energy."""
+    si = _golden("material.json")["silicon"]
+    assert abs(si["dEdx_min_MeV_cm2_per_g"] * si["X0_g_per_cm2"] * 1e-3 - si["mean_loss_GeV_per_X0"]) < 1e-12
+    det = S.detector_full()
+    assert abs(det.eloss_per_x0 - si["mean_loss_GeV_per_X0"]) <= 1e-3 * si["mean_loss_GeV_per_X0"]
+    g = orc.geometry(S.Detector(radii=(10.0,), x_over_x0=0.02, eloss_per_x0=si["mean_loss_GeV_per_X0"],
+                                mass=det.mass))
+    p = 1.0
+    s = np.array([10.0, 0.0, 0.0, p, 0.0, 0.0])
+    st, s2, _ = orc.material_one(g, 0, s, np.zeros((6, 6)))
+    assert st == 0
+    E0 = np.hypot(p, det.mass)
+    E1 = np.hypot(np.linalg.norm(s2[3:]), det.mass)
+    assert abs((E0 - E1) - 0.02 * 0.03630848) <= 1e-12
+    assert np.allclose(s2[3:] / np.linalg.norm(s2[3:]), [1.0, 0.0, 0.0], atol=0)  # the loss keeps the direction
