@@ -396,10 +396,19 @@ void kf_graph_destroy(kf_graph* graph);
  * writes the fastest mode / waves_per_block / blocks_per_cu into *cfg and its
  * average time into *best_ms (nullable).  The outputs in args are
  * overwritten like by any build.  Results are cached in the context per
- * (max_cands, precision, window_mode, power-of-two bucket of n_seeds, bins);
+ * (device architecture, digest of the kernel sources the library was built
+ * from, max_cands, precision, window_mode, power-of-two bucket of n_seeds,
+ * bins), so entries loaded from another device or library build never match;
  * a cached entry is returned without timing.  kf_autotune_save / _load
  * write and read the cache as one JSON object per line. */
 int32_t kf_build_autotune(kf_ctx* ctx, kf_build_cfg* cfg, const kf_build_args* args, int32_t reps, float* best_ms);
+/* kf_fit_autotune: synchronous.  Times kf_fit (args as given, outputs
+ * overwritten, reps calls per shape) at 64, 128 and 256 threads per block and
+ * keeps the fastest for this problem class (device architecture, kernel source
+ * digest, flags, power-of-two bucket of n); later kf_fit calls of that class
+ * launch with it.  A cached entry is returned without timing.  Outputs: the
+ * block size and its average time per call (nullable). */
+int32_t kf_fit_autotune(kf_ctx* ctx, const kf_fit_args* args, int32_t reps, int32_t* best_block, float* best_ms);
 int32_t kf_autotune_save(kf_ctx* ctx, const char* path);
 int32_t kf_autotune_load(kf_ctx* ctx, const char* path);
 

@@ -5,6 +5,7 @@ instruction selection disabled and multiply-add contraction limited to single
 expressions, then linked into one shared library next to this file.
 """
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -25,14 +26,28 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def source_digest():
+    """First 16 hex digits of the SHA-256 of every kernel source and the public header: compiled into the
+    library, it keys the autotune cache, so timings taken with other kernels are never reused."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp")))
+    files.append(os.path.join(HERE, "..", "include", "kfmi.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False, jobs=8):
     srcs = sources()
     objdir = tempfile.mkdtemp(prefix="kfmi_build_")
     objs = []
     procs = []
+    digest = f'-DKF_SOURCE_DIGEST="{source_digest()}"'
     for s in srcs:
         o = os.path.join(objdir, os.path.basename(s) + ".o")
-        cmd = [HIPCC] + COMMON + ["-c", s, "-o", o]
+        cmd = [HIPCC] + COMMON + [digest, "-c", s, "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, stderr=subprocess.PIPE, stdout=subprocess.PIPE), s))

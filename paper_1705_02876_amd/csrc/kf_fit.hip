@@ -506,6 +506,9 @@ int32_t kf_ctx_create(kf_ctx** out, int32_t device) {
   kf_ctx* c = new kf_ctx();
   c->device = device;
   c->num_cus = prop.multiProcessorCount;
+  std::snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+  for (char* ch = c->arch; *ch; ++ch)  // the name goes into cache keys: keep it free of separators and quotes
+    if (*ch == ':' || *ch == '"' || *ch == ' ') *ch = '.';
   *out = c;
   return KF_OK;
 }
@@ -588,7 +591,12 @@ int32_t kf_fit(kf_ctx* ctx, const kf_fit_args* a) {
                                 emit ? (KF_RES_FEATURES + 2) * a->ld_res : int64_t(0)});
   const bool narrow = ext < (int64_t(1) << 30);
   auto kern = (a->flags & KF_FIT_FP64) ? fit_kernel_f64 : (narrow ? fit_kernel : fit_kernel_i64);
-  kern<<<kfh::grid_for(a->n, 256), 256, 0, kfh::stream_of(a->stream)>>>(
+  int block = 256;  // tuned block size for this problem class, if kf_fit_autotune found one
+  if (!ctx->fit_tuned.empty()) {
+    auto it = ctx->fit_tuned.find(kfh::fit_tune_key(ctx, a->flags, a->n));
+    if (it != ctx->fit_tuned.end()) block = 64 * it->second.waves_per_block;
+  }
+  kern<<<kfh::grid_for(a->n, block), block, 0, kfh::stream_of(a->stream)>>>(
       a->n, a->ld, a->state_in, a->cov_in, a->charge, a->hit_idx, a->ld_idx, a->hit_pos, a->hit_cov, a->ldh,
       a->state_out, a->cov_out, a->chi2_out, a->nhits_out, a->status_out, ctx->dgeom,
       emit ? a->residual_out : nullptr, a->ld_res);

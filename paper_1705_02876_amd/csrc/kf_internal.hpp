@@ -12,6 +12,11 @@
 #include "../../include/kfmi.h"
 #include "kf_device.hpp"
 
+// digest of the kernel sources this library was built from (set by the build); keys the autotune cache
+#ifndef KF_SOURCE_DIGEST
+#define KF_SOURCE_DIGEST "unknown"
+#endif
+
 // one autotuned build launch configuration
 struct kf_tuned {
   int32_t mode = 0, waves_per_block = 0, blocks_per_cu = 0;
@@ -24,7 +29,9 @@ struct kf_ctx {
   kf_geometry geom{};
   kfd::Geom dgeom{};
   int num_cus = 0;
+  char arch[64] = {0};                    // gcnArchName of the device (keys the autotune cache)
   std::map<std::string, kf_tuned> tuned;  // autotune cache, key from kf_build_autotune
+  std::map<std::string, kf_tuned> fit_tuned;  // fit launches: waves_per_block holds the block size in waves
 };
 
 namespace kfh {
@@ -40,6 +47,9 @@ inline int32_t check_hip(hipError_t e, const char* what) {
 int32_t enter(kf_ctx* ctx);
 
 inline hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Cache key of a tuned fit launch (device architecture, source digest, precision flag, bucket of the track count).
+std::string fit_tune_key(const kf_ctx* ctx, uint32_t flags, int64_t n);
 
 inline unsigned grid_for(int64_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
 

@@ -19,16 +19,28 @@ struct kf_graph {
 
 namespace {
 
-std::string tune_key(const kf_build_cfg* cfg, int64_t n_seeds) {
+// Cache key of a tuned build launch: device architecture, the digest of the kernel sources, and the problem's
+// class (candidates, precision, window, power-of-two bucket of the seed count, bin grid).  Entries taken on
+// another device or with other kernels never match.
+std::string tune_key(const kf_ctx* ctx, const kf_build_cfg* cfg, int64_t n_seeds) {
   int bucket = 0;
   while ((int64_t(1) << (bucket + 1)) <= n_seeds && bucket < 62) ++bucket;
   char buf[160];
-  std::snprintf(buf, sizeof buf, "N%d_p%d_w%d_s2^%d_phi%d_eta%d", cfg->max_cands, cfg->precision, cfg->window_mode,
-                bucket, cfg->n_phi, cfg->n_eta);
+  std::snprintf(buf, sizeof buf, "%s_%s_N%d_p%d_w%d_s2^%d_phi%d_eta%d", ctx->arch, KF_SOURCE_DIGEST, cfg->max_cands,
+                cfg->precision, cfg->window_mode, bucket, cfg->n_phi, cfg->n_eta);
   return buf;
 }
 
 }  // namespace
+
+std::string kfh::fit_tune_key(const kf_ctx* ctx, uint32_t flags, int64_t n) {
+  int bucket = 0;
+  while ((int64_t(1) << (bucket + 1)) <= n && bucket < 62) ++bucket;
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s_%s_fit_f%u_n2^%d", ctx->arch, KF_SOURCE_DIGEST,
+                static_cast<unsigned>(flags & (KF_FIT_FP64 | KF_FIT_EMIT_RESIDUALS)), bucket);
+  return buf;
+}
 
 extern "C" {
 
@@ -75,7 +87,7 @@ int32_t kf_build_autotune(kf_ctx* ctx, kf_build_cfg* cfg, const kf_build_args* a
   if (int32_t rc = kfh::enter(ctx)) return rc;
   if (!cfg || !args) return set_error(KF_ERR_INVALID_ARG, "null argument");
   if (reps < 1 || reps > 1000) return set_error(KF_ERR_INVALID_ARG, "reps must be 1..1000");
-  const std::string key = tune_key(cfg, args->n_seeds);
+  const std::string key = tune_key(ctx, cfg, args->n_seeds);
   auto it = ctx->tuned.find(key);
   if (it != ctx->tuned.end()) {
     cfg->mode = it->second.mode;
@@ -138,6 +150,63 @@ int32_t kf_build_autotune(kf_ctx* ctx, kf_build_cfg* cfg, const kf_build_args* a
   return KF_OK;
 }
 
+int32_t kf_fit_autotune(kf_ctx* ctx, const kf_fit_args* args, int32_t reps, int32_t* best_block, float* best_ms) {
+  if (int32_t rc = kfh::enter(ctx)) return rc;
+  if (!args) return set_error(KF_ERR_INVALID_ARG, "null argument");
+  if (reps < 1 || reps > 1000) return set_error(KF_ERR_INVALID_ARG, "reps must be 1..1000");
+  const std::string key = kfh::fit_tune_key(ctx, args->flags, args->n);
+  auto it = ctx->fit_tuned.find(key);
+  if (it != ctx->fit_tuned.end()) {
+    if (best_block) *best_block = 64 * it->second.waves_per_block;
+    if (best_ms) *best_ms = it->second.ms;
+    return KF_OK;
+  }
+  if (args->n == 0) {
+    if (best_block) *best_block = 256;
+    if (best_ms) *best_ms = 0.f;
+    return KF_OK;
+  }
+  hipStream_t s = kfh::stream_of(args->stream);
+  hipEvent_t e0, e1;
+  if (int32_t rc = kfh::check_hip(hipEventCreate(&e0), "hipEventCreate")) return rc;
+  if (int32_t rc = kfh::check_hip(hipEventCreate(&e1), "hipEventCreate")) {
+    (void)hipEventDestroy(e0);
+    return rc;
+  }
+  kf_tuned best;
+  best.ms = INFINITY;
+  int32_t rc = KF_OK;
+  const int waves[3] = {1, 2, 4};  // 64, 128, 256 threads (the kernels' launch bound is 256)
+  for (int wi = 0; wi < 3 && rc == KF_OK; ++wi) {
+    kf_tuned t;
+    t.waves_per_block = waves[wi];
+    ctx->fit_tuned[key] = t;  // kf_fit launches with the candidate block size while it is timed
+    if ((rc = kf_fit(ctx, args)) != KF_OK) break;  // warm-up and validation
+    if ((rc = kfh::check_hip(hipEventRecord(e0, s), "hipEventRecord")) != KF_OK) break;
+    for (int r = 0; r < reps && rc == KF_OK; ++r) rc = kf_fit(ctx, args);
+    if (rc != KF_OK) break;
+    if ((rc = kfh::check_hip(hipEventRecord(e1, s), "hipEventRecord")) != KF_OK) break;
+    if ((rc = kfh::check_hip(hipEventSynchronize(e1), "hipEventSynchronize")) != KF_OK) break;
+    float ms = 0.f;
+    if ((rc = kfh::check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) != KF_OK) break;
+    ms /= static_cast<float>(reps);
+    if (ms < best.ms) {
+      best.waves_per_block = waves[wi];
+      best.ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != KF_OK) {
+    ctx->fit_tuned.erase(key);
+    return rc;
+  }
+  ctx->fit_tuned[key] = best;
+  if (best_block) *best_block = 64 * best.waves_per_block;
+  if (best_ms) *best_ms = best.ms;
+  return KF_OK;
+}
+
 int32_t kf_autotune_save(kf_ctx* ctx, const char* path) {
   if (!ctx || !path) return set_error(KF_ERR_INVALID_ARG, "null argument");
   std::FILE* f = std::fopen(path, "w");
@@ -146,6 +215,9 @@ int32_t kf_autotune_save(kf_ctx* ctx, const char* path) {
     std::fprintf(f, "{\"key\": \"%s\", \"mode\": %d, \"waves_per_block\": %d, \"blocks_per_cu\": %d, \"ms\": %.6g}\n",
                  kv.first.c_str(), kv.second.mode, kv.second.waves_per_block, kv.second.blocks_per_cu,
                  static_cast<double>(kv.second.ms));
+  for (const auto& kv : ctx->fit_tuned)
+    std::fprintf(f, "{\"key\": \"%s\", \"fit_block\": %d, \"ms\": %.6g}\n", kv.first.c_str(),
+                 64 * kv.second.waves_per_block, static_cast<double>(kv.second.ms));
   const bool ok = std::fclose(f) == 0;
   return ok ? KF_OK : set_error(KF_ERR_INVALID_ARG, "error writing %s", path);
 }
@@ -160,6 +232,17 @@ int32_t kf_autotune_load(kf_ctx* ctx, const char* path) {
     char key[161];
     kf_tuned t;
     double ms = 0.0;
+    int block = 0;
+    if (std::sscanf(line, " {\"key\": \"%160[^\"]\", \"fit_block\": %d, \"ms\": %lf", key, &block, &ms) == 3) {
+      if (block != 64 && block != 128 && block != 256) {
+        rc = set_error(KF_ERR_INVALID_ARG, "malformed fit autotune entry in %s", path);
+        break;
+      }
+      t.waves_per_block = block / 64;
+      t.ms = static_cast<float>(ms);
+      ctx->fit_tuned[key] = t;
+      continue;
+    }
     if (std::sscanf(line, " {\"key\": \"%160[^\"]\", \"mode\": %d, \"waves_per_block\": %d, \"blocks_per_cu\": %d, \"ms\": %lf",
                     key, &t.mode, &t.waves_per_block, &t.blocks_per_cu, &ms) != 5 ||
         (t.mode != KF_BUILD_TILED && t.mode != KF_BUILD_PERSISTENT) || t.waves_per_block < 1 ||

@@ -94,6 +94,8 @@ def load_library(path=LIB_PATH):
     lib.kf_update.argtypes = [P, I64, I64, P, P, P, P, I64, P, P, C.c_uint32, P]
     lib.kf_fit.restype = I32
     lib.kf_fit.argtypes = [P, P]
+    lib.kf_fit_autotune.restype = I32
+    lib.kf_fit_autotune.argtypes = [P, P, I32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
     lib.kf_smooth.restype = I32
     lib.kf_smooth.argtypes = [P, P]
     _declare_more(lib)
@@ -208,6 +210,22 @@ class Context:
 
     def kf_fit(self, state_in, cov_in, charge, hit_idx, hit_pos, hit_cov, state_out, cov_out, chi2_out, nhits_out,
                status_out, residual_out=None, n=None, stream=None, fp64=False):
+        a = self._fit_args(state_in, cov_in, charge, hit_idx, hit_pos, hit_cov, state_out, cov_out, chi2_out,
+                           nhits_out, status_out, residual_out, n, stream, fp64)
+        _check(_lib.kf_fit(self.h, C.byref(a)))
+
+    def kf_fit_autotune(self, state_in, cov_in, charge, hit_idx, hit_pos, hit_cov, state_out, cov_out, chi2_out,
+                        nhits_out, status_out, residual_out=None, n=None, stream=None, fp64=False, reps=5):
+        """kf_fit_autotune (synchronous): returns (block size, ms per call); later kf_fit calls of this problem
+        class launch with that block size."""
+        a = self._fit_args(state_in, cov_in, charge, hit_idx, hit_pos, hit_cov, state_out, cov_out, chi2_out,
+                           nhits_out, status_out, residual_out, n, stream, fp64)
+        block, ms = C.c_int32(0), C.c_float(0.0)
+        _check(_lib.kf_fit_autotune(self.h, C.byref(a), int(reps), C.byref(block), C.byref(ms)))
+        return block.value, ms.value
+
+    def _fit_args(self, state_in, cov_in, charge, hit_idx, hit_pos, hit_cov, state_out, cov_out, chi2_out, nhits_out,
+                  status_out, residual_out, n, stream, fp64):
         import torch
         for t, dt, nm in ((state_in, torch.float32, "state_in"), (cov_in, torch.float32, "cov_in"),
                           (charge, torch.int8, "charge"), (hit_idx, torch.int32, "hit_idx"),
@@ -230,7 +248,7 @@ class Context:
             a.residual_out = _ptr(residual_out)
             a.ld_res = residual_out.shape[1]
         a.stream = _stream(stream)
-        _check(_lib.kf_fit(self.h, C.byref(a)))
+        return a
 
     def kf_smooth(self, state_in, cov_in, charge, hit_idx, hit_pos, hit_cov, state_out, cov_out, status_out,
                   chi2_out=None, nhits_out=None, n=None, stream=None, fp64=False):
