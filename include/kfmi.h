@@ -333,6 +333,21 @@ typedef struct {
  * irrelevant; kf_build overwrites what it uses. */
 size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_events, int64_t n_seeds);
 int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* args);
+/* kf_build_noalloc: kf_build for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same configuration, arguments, kernels and results as
+ * kf_build, but args->workspace and args->workspace_bytes are ignored: the
+ * work queue, direction cells and seed order live in a static device array of
+ * KF_BUILD_NOALLOC_SCRATCH_BYTES (16 MiB) that each device the library runs on
+ * holds until the process ends.  The call allocates nothing.  It returns
+ * KF_ERR_WORKSPACE when kf_build_workspace_size(cfg, n_events, n_seeds)
+ * exceeds that maximum (with seed_order: about 8 KB per event plus 4 bytes per
+ * seed, e.g. 64 events and 3.9 M seeds).  Every call on a device shares that
+ * device's array and clears what must start at zero itself; calls that overlap
+ * on one device (other streams, other host threads, other contexts) race and
+ * must be serialised by the caller. */
+#define KF_BUILD_NOALLOC_SCRATCH_BYTES (16u << 20)
+int32_t kf_build_noalloc(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* args);
 
 
 /* ------------------------------------------------------------------------

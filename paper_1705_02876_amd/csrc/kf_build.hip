@@ -1301,8 +1301,56 @@ size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_events, int64_
   return (cfg->mode == KF_BUILD_PERSISTENT || cfg->seed_order) ? b : 0;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Static scratch of kf_build_noalloc: the work queue, direction cells and seed order that kf_build keeps in the
+// caller's workspace.  Each device the library runs on holds one copy until the process ends; kernels receive
+// its device address (kf_ctx::scratch, from hipGetSymbolAddress), never this host-side name.
+constexpr size_t kScratchBytes = KF_BUILD_NOALLOC_SCRATCH_BYTES;
+static_assert(kScratchBytes == (size_t(16) << 20), "scratch size");
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+int32_t build_impl(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a, void* workspace,
+                   size_t workspace_bytes);
+
+}  // namespace
+
+int32_t kfh::scratch_init(kf_ctx* ctx) {
+  void* ptr = nullptr;
+  if (int32_t rc = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))
+    return rc;
+  ctx->scratch = ptr;
+  ctx->scratch_bytes = kScratchBytes;
+  return KF_OK;
+}
+
+extern "C" {
+
 int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   if (int32_t rc = kfh::enter(ctx)) return rc;
+  if (!a) return set_error(KF_ERR_INVALID_ARG, "null args");
+  return build_impl(ctx, cfg, a, a->workspace, a->workspace_bytes);
+}
+
+int32_t kf_build_noalloc(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
+  if (int32_t rc = kfh::enter(ctx)) return rc;
+  if (!cfg || !a) return set_error(KF_ERR_INVALID_ARG, "null args");
+  if (!ctx->scratch) return set_error(KF_ERR_DEVICE, "static scratch not initialised for device %d", ctx->device);
+  const size_t need = kf_build_workspace_size(cfg, a->n_events, a->n_seeds);
+  if (need > ctx->scratch_bytes)
+    return set_error(KF_ERR_WORKSPACE, "kf_build_noalloc: this problem needs %zu bytes of scratch, the static maximum "
+                     "is %zu (use kf_build with a workspace)", need, ctx->scratch_bytes);
+  return build_impl(ctx, cfg, a, ctx->scratch, ctx->scratch_bytes);
+}
+
+}  // extern "C"
+
+namespace {
+
+int32_t build_impl(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a, void* workspace,
+                   size_t workspace_bytes) {
   if (!cfg || !a) return set_error(KF_ERR_INVALID_ARG, "null args");
   if (!ctx->has_geometry) return set_error(KF_ERR_GEOMETRY, "no geometry set");
   const int L = ctx->geom.n_layers;
@@ -1373,13 +1421,13 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   if (wpb > 4) return set_error(KF_ERR_INVALID_ARG, "waves_per_block must be 1..4");
   hipStream_t stream = kfh::stream_of(a->stream);
   const size_t need = kf_build_workspace_size(cfg, a->n_events, a->n_seeds);
-  if (need > 0 && (!a->workspace || a->workspace_bytes < need))
+  if (need > 0 && (!workspace || workspace_bytes < need))
     return set_error(KF_ERR_WORKSPACE, "this configuration needs kf_build_workspace_size() = %zu bytes of workspace",
                      need);
   p.order = nullptr;
   if (cfg->seed_order) {
     if (a->n_seeds > INT32_MAX) return set_error(KF_ERR_INVALID_ARG, "seed_order needs n_seeds < 2^31");
-    unsigned char* w = static_cast<unsigned char*>(a->workspace);
+    unsigned char* w = static_cast<unsigned char*>(workspace);
     int32_t* cells = reinterpret_cast<int32_t*>(w + kQueueBytes);
     int32_t* order = reinterpret_cast<int32_t*>(w + kQueueBytes + cells_bytes(a->n_events));
     const int64_t nc = a->n_events * kSeedCells;
@@ -1408,7 +1456,7 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
     launch_any(G, lc, p);
     return kfh::check_hip(hipGetLastError(), "build_tiled_kernel launch");
   }
-  p.queue = static_cast<int32_t*>(a->workspace);
+  p.queue = static_cast<int32_t*>(workspace);
   fill_i32_kernel<<<1, 64, 0, stream>>>(p.queue, kXcds, 0);
   const int bpc = cfg->blocks_per_cu > 0 ? cfg->blocks_per_cu : 2;
   lc.persistent = true;
@@ -1417,4 +1465,4 @@ int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a) {
   return kfh::check_hip(hipGetLastError(), "build_persistent_kernel launch");
 }
 
-}  // extern "C"
+}  // namespace

@@ -509,6 +509,14 @@ int32_t kf_ctx_create(kf_ctx** out, int32_t device) {
   std::snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
   for (char* ch = c->arch; *ch; ++ch)  // the name goes into cache keys: keep it free of separators and quotes
     if (*ch == ':' || *ch == '"' || *ch == ' ') *ch = '.';
+  if (int32_t rc = kfh::check_hip(hipSetDevice(device), "hipSetDevice")) {
+    delete c;
+    return rc;
+  }
+  if (int32_t rc = kfh::scratch_init(c)) {
+    delete c;
+    return rc;
+  }
   *out = c;
   return KF_OK;
 }

@@ -32,6 +32,8 @@ struct kf_ctx {
   char arch[64] = {0};                    // gcnArchName of the device (keys the autotune cache)
   std::map<std::string, kf_tuned> tuned;  // autotune cache, key from kf_build_autotune
   std::map<std::string, kf_tuned> fit_tuned;  // fit launches: waves_per_block holds the block size in waves
+  void* scratch = nullptr;                    // device address of this device's static build scratch
+  size_t scratch_bytes = 0;
 };
 
 namespace kfh {
@@ -47,6 +49,9 @@ inline int32_t check_hip(hipError_t e, const char* what) {
 int32_t enter(kf_ctx* ctx);
 
 inline hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Looks up the device address of the static build scratch on ctx's (current) device.
+int32_t scratch_init(kf_ctx* ctx);
 
 // Cache key of a tuned fit launch (device architecture, source digest, precision flag, bucket of the track count).
 std::string fit_tune_key(const kf_ctx* ctx, uint32_t flags, int64_t n);

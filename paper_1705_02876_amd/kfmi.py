@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "kfmi.h")
 MAX_LAYERS = 32
 
 KF_OK = 0
+KF_ERR_INVALID_ARG, KF_ERR_GEOMETRY, KF_ERR_DEVICE, KF_ERR_UNSUPPORTED, KF_ERR_WORKSPACE = -1, -2, -3, -4, -5
 ST_NO_CROSSING, ST_OUT_OF_Z, ST_NONFINITE, ST_NOT_PD, ST_STOPPED = 1, 2, 4, 8, 16
 UPDATE_CHI2_ONLY = 1
 FIT_EMIT_RESIDUALS = 1

@@ -51,6 +51,8 @@ def declare(lib):
     lib.kf_build_workspace_size.argtypes = [P, I64, I64]
     lib.kf_build.restype = I32
     lib.kf_build.argtypes = [P, P, P]
+    lib.kf_build_noalloc.restype = I32
+    lib.kf_build_noalloc.argtypes = [P, P, P]
     lib.kf_graph_begin.restype = I32
     lib.kf_graph_begin.argtypes = [P, P]
     lib.kf_graph_end.restype = I32
@@ -143,8 +145,9 @@ def workspace_bytes(cfg, n_events, n_seeds):
 
 
 def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=None, counters=None, workspace=None,
-          stream=None, mlp_packed=None, check=True):
-    """kf_build.  seeds: dict(offsets int64 (E+1), state (6,ld), cov (21,ld), charge int8 (S), hits int32 (3,ld), n).
+          stream=None, mlp_packed=None, check=True, noalloc=False):
+    """kf_build (kf_build_noalloc with noalloc=True: no workspace, the library's static scratch instead).
+    seeds: dict(offsets int64 (E+1), state (6,ld), cov (21,ld), charge int8 (S), hits int32 (3,ld), n).
 
     Returns dict of device tensors (n_cands, cand_hits (L,S,N), cand_chi2 (S,N), cand_nhits, cand_status,
     best_state, best_cov)."""
@@ -175,7 +178,9 @@ def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=Non
                    cand_status=torch.empty(max(S, 1), N, dtype=torch.int32, device=dev),
                    best_state=torch.empty(6, ld, dtype=torch.float32, device=dev),
                    best_cov=torch.empty(21, ld, dtype=torch.float32, device=dev))
-    wsb = workspace_bytes(cfg, n_events, S)
+    wsb = 0 if noalloc else workspace_bytes(cfg, n_events, S)
+    if noalloc and workspace is not None:
+        raise ValueError("kf_build_noalloc takes no workspace")
     if workspace is None and wsb > 0:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
     if workspace is not None and workspace.numel() < wsb:
@@ -202,7 +207,7 @@ def build(ctx, cfg, seeds, bins, layer_offsets, n_events, first_layer=3, out=Non
     # kept for kf_build_autotune, with every tensor the pointers refer to
     out["_args"] = a
     out["_keep"] = (seeds, bins, layer_offsets, workspace, mlp_packed, counters)
-    kfmi._check(lib.kf_build(ctx.h, C.byref(cfg), C.byref(a)))
+    kfmi._check((lib.kf_build_noalloc if noalloc else lib.kf_build)(ctx.h, C.byref(cfg), C.byref(a)))
     return out
 
 
