@@ -283,152 +283,108 @@ def physics_leg(ctx, bp, seeds, hits, bins, bout, cfg):
     return {"combinatorial": dict(pick(comb), max_cands=int(cfg.max_cands)), "best_hit": pick(best)}
 
 
-def pipeline_leg(ctx, bp, cfg, bout, resident_ms, n_chunks=4, reps=3):
-    """End to end with the events in pinned host memory (the paper measured transfers at about half of its GPU
-    build time): chunks of whole events are copied in, binned, built and their outputs copied out.  Input copies,
-    kernels and output copies run on three streams linked by events, with three device input slots, so the
-    copies of other chunks overlap a chunk's kernels.  The chunks' candidates are checked against the resident
-    build's (untimed)."""
+def serial_leg(ctx, bp, seeds, hits, bins, bout, cfg, grouped_ms, reps=3):
+    """The serial-candidate mapping (Sec. 4.3's proposed one thread per seed: one lane holds a seed's
+    candidates and takes them one after the other) against the grouped mapping the step times (a seed's
+    candidates in consecutive lanes), on the same binned events; outputs checked equal (untimed)."""
     import torch
-    from paper_1705_02876_amd import synth as S, kfmi, kfmi_build as KB
-    L = ctx.n_layers
-    E = bp.n_events
-    lo = np.asarray(bp.layer_hit_offsets, np.int64)
-    so = np.asarray(bp.seed_offsets, np.int64)
-    n_seeds = int(so[-1])
-    # events dealt to the chunks round robin (chunk k: events k, k + n, ...), so that every chunk holds a like mix
-    # of dense and sparse events and its launches run about as efficiently as one launch over all events
-    groups = [list(range(k, E, n_chunks)) for k in range(n_chunks) if k < E]
-    pin = lambda a, dt: torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=dt))).pin_memory()
-    host, dev_out, dev_bins, host_out = [], [], [], []
-    h2d_bytes = 0
-    for evs in groups:
-        hsl = [(int(lo[e * L]), int(lo[(e + 1) * L])) for e in evs]
-        ssl = [(int(so[e]), int(so[e + 1])) for e in evs]
-        hb = np.concatenate([[0], np.cumsum([h1 - h0 for h0, h1 in hsl])])  # chunk hit base of each event
-        sb = np.concatenate([[0], np.cumsum([s1 - s0 for s0, s1 in ssl])])
-        hidx = np.concatenate([np.arange(h0, h1) for h0, h1 in hsl])
-        sidx = np.concatenate([np.arange(s0, s1) for s0, s1 in ssl])
-        lofs = np.concatenate([lo[e * L:(e + 1) * L] - lo[e * L] + hb[i] for i, e in enumerate(evs)] + [[hb[-1]]])
-        shits = np.concatenate([bp.seed_hits[s0:s1] - h0 + hb[i] for i, ((s0, s1), (h0, _)) in
-                                enumerate(zip(ssl, hsl))])
-        c = dict(ne=len(evs), nh=int(hb[-1]), ns=int(sb[-1]), evs=evs, hsl=hsl, ssl=ssl, hb=hb, sb=sb,
-                 pos=pin(bp.hit_pos[hidx].T, np.float32), cov=pin(bp.hit_cov[hidx].T, np.float32),
-                 lofs=pin(lofs, np.int64), soff=pin(sb, np.int64),
-                 sst=pin(bp.seed_state[sidx].T, np.float32), scv=pin(S.pack6(bp.seed_cov[sidx]).T, np.float32),
-                 sq=pin(bp.seed_q[sidx], np.int8), shit=pin(shits.T, np.int32))
-        h2d_bytes += sum(c[k].numel() * c[k].element_size() for k in ("pos", "cov", "lofs", "soff", "sst", "scv",
-                                                                         "sq", "shit"))
-        host.append(c)
-    cap = {k: max(c[k].numel() for c in host) for k in ("pos", "cov", "lofs", "soff", "sst", "scv", "sq", "shit")}
-    dt = {"pos": torch.float32, "cov": torch.float32, "lofs": torch.int64, "soff": torch.int64,
-          "sst": torch.float32, "scv": torch.float32, "sq": torch.int8, "shit": torch.int32}
-    n_slots = 3
-    slots = [{k: torch.empty(cap[k], dtype=dt[k], device="cuda") for k in cap} for _ in range(n_slots)]
-    max_nh, max_ns = max(c["nh"] for c in host), max(c["ns"] for c in host)
-    bws = torch.empty(max(kfmi.load_library().kf_bin_hits_workspace_size(max_nh, max(c["ne"] for c in host)), 4),
-                      dtype=torch.uint8,
-                      device="cuda")
-    ws = torch.empty(max(KB.workspace_bytes(cfg, max(c["ne"] for c in host), max_ns), 1), dtype=torch.uint8,
-                     device="cuda")
-    s_in, s_run, s_out = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
-    ev_in = [torch.cuda.Event() for _ in host]
-    ev_run = [torch.cuda.Event() for _ in host]
-    outs_keys = ("n_cands", "cand_hits", "cand_chi2", "cand_nhits", "cand_status", "best_state", "best_cov")
-
-    def views(k, c):
-        d = slots[k % n_slots]
-        v = {key: d[key][:c[key].numel()].view(c[key].shape) for key in cap}
-        return v
-
-    def h2d(k, c):
-        with torch.cuda.stream(s_in):
-            if k >= n_slots:
-                s_in.wait_event(ev_run[k - n_slots])  # the slot's previous chunk has been binned and built
-            v = views(k, c)
-            for key in cap:
-                v[key].copy_(c[key], non_blocking=True)
-            ev_in[k].record(s_in)
-
-    def kernels(k, c, check=False):
-        with torch.cuda.stream(s_run):
-            s_run.wait_event(ev_in[k])
-            v = views(k, c)
-            seeds = dict(offsets=v["soff"], state=v["sst"], cov=v["scv"], charge=v["sq"], hits=v["shit"], n=c["ns"])
-            first = k >= len(dev_out)
-            b = KB.bin_hits(ctx, v["lofs"], v["pos"], v["cov"], c["ne"], n_phi=cfg.n_phi, n_eta=cfg.n_eta,
-                            out=None if first else dev_bins[k], workspace=bws, stream=s_run, check=check)
-            o = KB.build(ctx, cfg, seeds, b, v["lofs"], c["ne"], out=None if first else dev_out[k], workspace=ws,
-                         stream=s_run, check=check)
-            if first:
-                dev_bins.append(b)
-                dev_out.append(o)
-                host_out.append({key: torch.empty(o[key].shape, dtype=o[key].dtype).pin_memory()
-                                 for key in outs_keys})
-            ev_run[k].record(s_run)
-
-    def d2h(k):
-        with torch.cuda.stream(s_out):
-            s_out.wait_event(ev_run[k])
-            for key in outs_keys:
-                host_out[k][key].copy_(dev_out[k][key], non_blocking=True)
-
-    def run_all(with_kernels=True, check=False):
-        # inputs one chunk ahead of the kernels (an event is waited for only after it has been recorded)
-        h2d(0, host[0])
-        for k, c in enumerate(host):
-            if k + 1 < len(host):
-                if with_kernels or k + 1 < n_slots:
-                    h2d(k + 1, host[k + 1])
-                else:
-                    with torch.cuda.stream(s_in):  # copies only: no kernels free the slots
-                        v = views(k + 1, host[k + 1])
-                        for key in cap:
-                            v[key].copy_(host[k + 1][key], non_blocking=True)
-            if with_kernels:
-                kernels(k, c, check=check)
-            else:
-                ev_run[k].record(s_in)
-            d2h(k)
-
-    # first pass (untimed): allocates the chunks' device outputs and checks the candidates
-    run_all(check=True)
-    torch.cuda.synchronize()
+    from paper_1705_02876_amd import kfmi_build as KB
+    keys = ("n_cands", "cand_hits", "cand_chi2", "cand_nhits", "cand_status", "best_state", "best_cov")
+    best = {}
     ok = True
-    rb = bout["cand_hits"].cpu().numpy()
-    for k, c in enumerate(host):
-        ch = host_out[k]["cand_hits"].numpy()[:, :c["ns"], :].astype(np.int64)
-        for i, e in enumerate(c["evs"]):
-            (s0, s1), (h0, _) = c["ssl"][i], c["hsl"][i]
-            part = ch[:, c["sb"][i]:c["sb"][i + 1], :]
-            part = np.where(part >= 0, part - c["hb"][i] + h0, part)
-            ok &= bool(np.array_equal(part, rb[:, s0:s1, :]))
-    d2h_bytes = sum(host_out[k][key].numel() * host_out[k][key].element_size() for k in range(len(host)) for key in outs_keys)
+    for wpb in (1, 2, 4):
+        c = KB.make_cfg(max_cands=cfg.max_cands, mode=KB.BUILD_SERIAL, precision=cfg.precision, n_phi=cfg.n_phi,
+                        n_eta=cfg.n_eta, waves_per_block=wpb)
+        ws = torch.empty(KB.workspace_bytes(c, bp.n_events, seeds["n"]), dtype=torch.uint8, device="cuda")
+        o = KB.build(ctx, c, seeds, bins, hits["layer_offsets"], bp.n_events, workspace=ws)
+        torch.cuda.synchronize()
+        ok &= all(torch.equal(torch.nan_to_num(o[k], nan=-7.0), torch.nan_to_num(bout[k], nan=-7.0)) for k in keys)
+        t = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            KB.build(ctx, c, seeds, bins, hits["layer_offsets"], bp.n_events, out=o, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            t = min(t, e0.elapsed_time(e1))
+        best[wpb] = t
+        del o, ws
+    ms = min(best.values())
+    return {"build_ms": ms, "build_ms_by_waves_per_block": best, "grouped_build_ms": grouped_ms,
+            "speed_vs_grouped": grouped_ms / ms, "outputs_equal_grouped": bool(ok),
+            "note": "one lane per seed, its candidates in two device buffers; best of %d per launch shape" % reps}
 
-    def timed(with_kernels):
+
+def pipeline_leg(ctx, bp, cfg, bout, resident_ms, n_chunks=8, n_slots=4, reps=3):
+    """End to end with the events in page-locked host memory (the paper measured transfers at about half of its
+    GPU build time), through kf_build_host: chunks of consecutive events are copied in, binned, built and their
+    outputs copied back, with input copies, kernels and output copies on three library streams.  Its outputs are
+    checked against the resident build's (untimed).  The copies alone are timed as the same bytes moved by two
+    plain copies running together (inputs in, outputs out)."""
+    import torch
+    from paper_1705_02876_amd import kfmi_build as KB
+    hp = KB.host_problem(bp)
+    ws = torch.empty(KB.build_host_workspace_bytes(ctx, cfg, hp, n_chunks, n_slots), dtype=torch.uint8, device="cuda")
+    out = KB.build_host(ctx, cfg, hp, n_chunks=n_chunks, n_slots=n_slots, workspace=ws)
+    torch.cuda.synchronize()
+    S_ = hp["n_seeds"]
+    keys = ("n_cands", "cand_hits", "cand_chi2", "cand_nhits", "cand_status", "best_state", "best_cov")
+    res = {k: (bout[k][..., :S_] if k in ("best_state", "best_cov") else
+               (bout[k][:, :S_] if k == "cand_hits" else bout[k][:S_])).cpu().numpy() for k in keys}
+    ok = all(np.array_equal(out[k].numpy(), res[k], equal_nan=True) for k in keys)
+    in_keys = ("layer_offsets", "pos", "cov", "seed_offsets", "state", "scov", "charge", "hits")
+    h2d_bytes = sum(hp[k].numel() * hp[k].element_size() for k in in_keys)
+    d2h_bytes = sum(out[k].numel() * out[k].element_size() for k in keys)
+    main = torch.cuda.current_stream()
+
+    def timed(fn):
         best = float("inf")
         for _ in range(reps):
-            main = torch.cuda.current_stream()
             t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             t0.record(main)
-            for st in (s_in, s_run, s_out):
-                st.wait_event(t0)
-            run_all(with_kernels)
-            for st in (s_in, s_run, s_out):
-                main.wait_stream(st)
+            fn()
             t1.record(main)
             torch.cuda.synchronize()
             best = min(best, t0.elapsed_time(t1))
         return best
 
-    ms = timed(True)
-    copies_ms = timed(False)
-    return {"chunks": len(host), "events": E, "seeds": n_seeds, "h2d_bytes": int(h2d_bytes), "d2h_bytes": int(d2h_bytes),
-            "end_to_end_ms": ms, "seeds_per_s_end_to_end": n_seeds / (ms * 1e-3),
+    ms = timed(lambda: KB.build_host(ctx, cfg, hp, n_chunks=n_chunks, n_slots=n_slots, out=out, workspace=ws))
+    by_chunks = {n_chunks: ms}
+    for nc in (4, 16):  # other chunkings, timed the same way (the workspace is sized for each)
+        if nc == n_chunks or nc > bp.n_events:
+            continue
+        w2 = torch.empty(KB.build_host_workspace_bytes(ctx, cfg, hp, nc, n_slots), dtype=torch.uint8, device="cuda")
+        by_chunks[nc] = timed(lambda: KB.build_host(ctx, cfg, hp, n_chunks=nc, n_slots=n_slots, out=out,
+                                                    workspace=w2))
+        del w2
+    dev_in = {k: torch.empty(hp[k].shape, dtype=hp[k].dtype, device="cuda") for k in in_keys}
+    s_a, s_b = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def copies():
+        ev = torch.cuda.Event()
+        ev.record(main)
+        for s in (s_a, s_b):
+            s.wait_event(ev)
+        with torch.cuda.stream(s_a):
+            for k in in_keys:
+                dev_in[k].copy_(hp[k], non_blocking=True)
+        with torch.cuda.stream(s_b):
+            for k in keys:
+                out[k].copy_(bout[k], non_blocking=True)
+        main.wait_stream(s_a)
+        main.wait_stream(s_b)
+
+    copies_ms = timed(copies)
+    return {"chunks": n_chunks, "slots": n_slots, "end_to_end_ms_by_chunks": by_chunks,
+            "events": int(bp.n_events), "seeds": int(S_),
+            "h2d_bytes": int(h2d_bytes), "d2h_bytes": int(d2h_bytes),
+            "end_to_end_ms": ms, "seeds_per_s_end_to_end": S_ / (ms * 1e-3),
             "copies_only_ms": copies_ms, "copy_gb_per_s": (h2d_bytes + d2h_bytes) / (copies_ms * 1e-3) / 1e9,
-            "resident_bin_build_ms": resident_ms, "candidates_equal_resident": ok,
-            "note": "best of %d passes; events in pinned host memory, input copies / kernels / output copies on three streams, outputs copied back" % reps}
+            "resident_bin_build_ms": resident_ms, "outputs_equal_resident": bool(ok),
+            "note": "kf_build_host, best of %d passes; events in page-locked host memory, %d chunks of consecutive "
+                    "events with equal seed counts, %d device slots; copies-only time: the same bytes in two plain "
+                    "copies running together" % (reps, n_chunks, n_slots)}
 
 
 def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, plain_build_ms):
@@ -475,6 +431,27 @@ def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, pl
     e_plain = judge.judge_problem(bp, bout["cand_hits"][:, :S_, 0].T.cpu().numpy())
     e_learn = judge.judge_problem(bp, lout["cand_hits"][:, :S_, 0].T.cpu().numpy())
     c = cnt.cpu().numpy()
+    # equal-efficiency comparison: the plain window with tighter chi2 cuts, at the plain build's launch shape
+    ablation = []
+    for cut in (10.0, 15.0, 20.0):
+        acfg = KB.make_cfg(max_cands=N, mode=cfg.mode, precision=cfg.precision, waves_per_block=cfg.waves_per_block,
+                           blocks_per_cu=cfg.blocks_per_cu, n_phi=cfg.n_phi, n_eta=cfg.n_eta, chi2_cut=cut)
+        acnt = torch.zeros(KB.BUILD_COUNTERS, dtype=torch.int64, device="cuda")
+        aout = KB.build(ctx, acfg, seeds, bins, hits["layer_offsets"], bp.n_events, counters=acnt, workspace=lws)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(3):
+            a, b = E(), E()
+            a.record(stream)
+            KB.build(ctx, acfg, seeds, bins, hits["layer_offsets"], bp.n_events, out=aout, workspace=lws)
+            b.record(stream)
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b))
+        ej = judge.judge_problem(bp, aout["cand_hits"][:, :seeds["n"], 0].T.cpu().numpy())
+        ac = acnt.cpu().numpy()
+        ablation.append({"chi2_cut": cut, "build_ms": best, "eff": ej["eff"], "fake_rate": ej["fake_rate"],
+                         "chi2_evals": int(ac[1]), "box_tests": int(ac[0])})
+        del aout
     return {"nsigma": args.nsigma, "build_mode": "persistent" if lcfg.mode == KB.BUILD_PERSISTENT else "tiled",
             "waves_per_block": int(lcfg.waves_per_block), "blocks_per_cu": int(lcfg.blocks_per_cu),
             "build_ms": lms, "plain_build_ms": plain_build_ms,
@@ -487,6 +464,10 @@ def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, pl
                          "cand_layer_steps": int(c[3]), "updates": int(c[4]), "fallback_passes": int(c[5])},
             "train_records": int(n_rec), "train_tracks": int(fit_dev["n"]), "train_steps": args.train_steps,
             "train_ms": train_ms, "train_ms_per_step": train_ms / max(args.train_steps, 1),
+            "plain_tighter_cut": ablation,
+            "plain_tighter_cut_note": "plain window with a tighter chi2 cut (best of 3 each, plain launch shape): "
+                                      "the same events judged the same way, to compare the learned window with a "
+                                      "plain window of like efficiency",
             "_best": lout["cand_hits"][:, :S_, 0].T.cpu().numpy()}
 
 
@@ -512,6 +493,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-window leg")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the end-to-end leg from pinned host memory")
     ap.add_argument("--no-smoother", action="store_true", help="skip the smoother leg")
+    ap.add_argument("--no-serial", action="store_true", help="skip the serial-candidate (one lane per seed) leg")
     ap.add_argument("--nsigma", type=float, default=2.5, help="learned window half width in network scales")
     ap.add_argument("--train-tracks", type=int, default=625_000, help="fit tracks whose residuals train the window")
     ap.add_argument("--train-steps", type=int, default=300)
@@ -714,6 +696,8 @@ def main():
         out["smoother"] = smooth_leg(ctx, fp, dict(state=st_in, cov=cv_in, q=q, hidx=hidx, hpos=hpos, hcov=hcov, n=n),
                                      L, fp64=args.fit_fp64)
     out["physics"] = physics_leg(ctx, bp, seeds, hits, bins, bout, cfg)
+    if not args.no_serial and cfg.precision == KB.PREC_F32:
+        out["serial_candidates"] = serial_leg(ctx, bp, seeds, hits, bins, bout, cfg, build_ms)
     if not args.no_pipeline:
         out["pipeline"] = pipeline_leg(ctx, bp, cfg, bout, bin_ms + build_ms)
     if not args.no_learned:

@@ -270,8 +270,13 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* args);
  *   box-tested, chi2 evaluations, compatible hits, candidate-layer steps,
  *   survivor updates with a hit, learned-window fallbacks to the plain window.
  * Modes: KF_BUILD_TILED (default) runs every layer of a tile of seeds inside
- * one launch; KF_BUILD_PERSISTENT launches one grid sized to the device
- * whose waves pull tiles from a device work queue (needs workspace).
+ * one launch, a seed's candidates in consecutive lanes of a wave;
+ * KF_BUILD_PERSISTENT launches one grid sized to the device whose waves pull
+ * tiles from a device work queue (needs workspace); KF_BUILD_SERIAL gives one
+ * lane to each seed, which takes its candidates one after the other (Sec. 4.3's
+ * proposed one thread per seed), with the candidates in workspace buffers
+ * (plain window, KF_PREC_F32 only; about 240 * max_cands bytes per seed of
+ * workspace).  The results do not depend on the mode.
  * Windows: a candidate's compatible hits are those with chi2 < chi2_cut.  The
  * plain window (KF_WINDOW_PLAIN) only limits the bins scanned: it bounds the
  * chi2 < chi2_cut region, so it changes no result.  KF_WINDOW_LEARNED (a
@@ -284,6 +289,7 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* args);
 #define KF_BUILD_COUNTERS 6
 #define KF_BUILD_TILED 0
 #define KF_BUILD_PERSISTENT 1
+#define KF_BUILD_SERIAL 2
 #define KF_WINDOW_PLAIN 0
 #define KF_WINDOW_LEARNED 1
 #define KF_PREC_F32 0
@@ -293,7 +299,7 @@ typedef struct {
   float chi2_cut;      /* > 0 */
   int32_t n_phi, n_eta;
   float window_margin; /* relative margin on the window half widths, >= 0 */
-  int32_t mode;        /* KF_BUILD_TILED or KF_BUILD_PERSISTENT */
+  int32_t mode;        /* KF_BUILD_TILED, KF_BUILD_PERSISTENT or KF_BUILD_SERIAL */
   int32_t window_mode; /* KF_WINDOW_PLAIN or KF_WINDOW_LEARNED */
   int32_t waves_per_block; /* 0 = library choice */
   int32_t blocks_per_cu;   /* persistent mode occupancy, 0 = library choice */
@@ -333,6 +339,66 @@ typedef struct {
  * irrelevant; kf_build overwrites what it uses. */
 size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_events, int64_t n_seeds);
 int32_t kf_build(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* args);
+/* ------------------------------------------------------------------------
+ * Binning and building from host memory with the transfers overlapped
+ * (Sec. 4.2: streams let transfers overlap computation; Sec. 4.3: transfers
+ * took about half of the GPU build time).  The events are cut into n_chunks
+ * runs of consecutive events with about equal seed counts; each chunk's hits
+ * and seeds are copied to the device, binned (kf_bin_hits with cfg's grid) and
+ * built (kf_build with cfg), and its outputs are copied into the host output
+ * arrays at the chunk's seeds.  Input copies and output copies run on two
+ * library streams and the kernels on two more (consecutive chunks alternate,
+ * so one chunk's launch tail overlaps the next chunk's kernels), all linked by
+ * events, with n_slots device slots for a chunk's inputs and outputs: the
+ * copies of one chunk overlap the kernels of others.  The results equal one
+ * kf_build over all events (hit indices are global).
+ * Inputs (HOST; page-locked memory lets the copies overlap), the layouts of
+ * kf_bin_hits and kf_build with leading dimensions n_hits and n_seeds:
+ *   layer_offsets [n_events * n_layers + 1] (from 0 to n_hits, every (event,
+ *   layer) below 2^24 - 1 hits), hit_pos [3][n_hits], hit_cov [6][n_hits],
+ *   seed_offsets [n_events + 1] (from 0 to n_seeds), seed_state
+ *   [6][n_seeds], seed_cov [21][n_seeds], seed_charge [n_seeds], seed_hits
+ *   [3][n_seeds] (global hit indices).
+ * Outputs (HOST), as kf_build's with S = n_seeds: n_cands [S], cand_hits
+ *   [n_layers][S][N], cand_chi2, cand_nhits, cand_status [S][N], best_state
+ *   [6][S] and best_cov [21][S] (nullable together).  counters (DEVICE,
+ *   nullable) accumulate as in kf_build; mlp_packed (DEVICE) as in kf_build.
+ * Workspace (DEVICE): kf_build_host_workspace_size() bytes (0 if the offsets
+ *   are invalid): n_slots chunk slots sized by the largest chunk, plus the
+ *   binning and building scratch of each kernel stream.
+ * Ordering: the call's work starts after the work already queued on
+ * `stream`, and `stream` waits for all of it: the host outputs are complete
+ * once `stream` has been synchronised; inputs, outputs and workspace must stay
+ * valid until then.  The host offsets are read during the call. */
+typedef struct {
+  int64_t n_events, n_seeds, n_hits;
+  int32_t first_layer;
+  int32_t n_chunks; /* 1 .. n_events */
+  int32_t n_slots;  /* 1 .. 4 device chunk slots (3 or 4 overlap copies with two chunks' kernels) */
+  const int64_t* layer_offsets;
+  const float* hit_pos;
+  const float* hit_cov;
+  const int64_t* seed_offsets;
+  const float* seed_state;
+  const float* seed_cov;
+  const int8_t* seed_charge;
+  const int32_t* seed_hits;
+  int32_t* n_cands;
+  int32_t* cand_hits;
+  float* cand_chi2;
+  int32_t* cand_nhits;
+  int32_t* cand_status;
+  float* best_state;
+  float* best_cov;
+  uint64_t* counters;
+  const void* mlp_packed;
+  void* workspace;
+  size_t workspace_bytes;
+  void* stream;
+} kf_build_host_args;
+size_t kf_build_host_workspace_size(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_host_args* args);
+int32_t kf_build_host(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_host_args* args);
+
 /* kf_build_noalloc: kf_build for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation).  Same configuration, arguments, kernels and results as
@@ -405,9 +471,11 @@ int32_t kf_graph_launch(kf_graph* graph, void* stream);
 void kf_graph_destroy(kf_graph* graph);
 
 /* kf_build_autotune: synchronous.  Times kf_build (cfg as given, args as
- * given, counters ignored) over the launch shapes {tiled, persistent} x
- * waves_per_block {1, 2, 4} x blocks_per_cu {1, 2, 4, 8} (persistent only if
- * args carries a large enough workspace), `reps` timed runs each after one warm-up, and
+ * given, counters ignored) over the launch shapes {tiled, persistent,
+ * serial} x waves_per_block {1, 2, 4} x blocks_per_cu {1, 2, 4, 8}
+ * (persistent only, serial only, if args carries a large enough workspace;
+ * serial only for the plain window in single precision), `reps` timed runs
+ * each after one warm-up, and
  * writes the fastest mode / waves_per_block / blocks_per_cu into *cfg and its
  * average time into *best_ms (nullable).  The outputs in args are
  * overwritten like by any build.  Results are cached in the context per

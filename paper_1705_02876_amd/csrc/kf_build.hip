@@ -36,6 +36,7 @@ constexpr int kQueueCap = 64 + 64 * kScanUnroll;  // box-passing (candidate, slo
 constexpr int kQueueDefer = 256;                  // learned window: pairs outside the learned box, deferred
 constexpr int kXcds = 8;                          // accelerator dies of the device (work-queue chunks)
 constexpr int kRangeChunk = 4;                    // slot ranges per candidate flattened together
+constexpr int kSerialMax = 8;                     // serial-candidate build: candidates per seed (max_cands <= 8)
 
 __device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, double zh, int n_phi, int n_eta) {
 #pragma clang fp contract(off)
@@ -355,6 +356,8 @@ struct BuildP {
   const int32_t* order;      // tile position -> seed index (seeds grouped by direction), or null
   const unsigned char* mlp;  // packed search-window network, or null for the plain window
   float nsigma;
+  float* cand_buf;  // serial-candidate build: two candidate buffers [2][kSerialWords][max_cands][buf_ld]
+  int64_t buf_ld;   // tile positions (tiles x 64)
   Geom g;
 };
 
@@ -440,6 +443,13 @@ struct ScanLds {
   uint8_t qb_own[LW ? kQueueDefer : 1];
 };
 
+// The per-layer back-pointers of the candidates (parent slot, hit) stay in LDS for the plain window,
+// [layers from first_layer][64] per wave after the scan tables, so that the backtrack at the end of a tile reads
+// LDS and cand_hits is written once; with the learned window (whose staged network weights already take the
+// block's LDS) they go to the cand_hits output array and are rewritten there in place.
+template <bool LW>
+constexpr bool kBackLds = !LW;
+
 // orders this lane's LDS accesses of the wave before and after (the wave executes in lockstep; this keeps the
 // compiler from moving LDS accesses across the point)
 __device__ __forceinline__ void wave_lds_sync() {
@@ -452,6 +462,365 @@ __device__ __forceinline__ int wave_max_i(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
   return v;
+}
+
+// Scans the plain window of this lane's candidate (the wave's 64 candidates together) and leaves in
+// lkey / lidx / lslot the candidate's best children by (chi2, hit index): their accumulated chi2, hit index
+// within the (event, layer) and slot, cnt of them (at most N); with the learned window, the definition of the
+// learned search window with its fallback (see below).  Wave-uniform work counters are accumulated.
+template <int Q, typename T, bool LW>
+__device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, const unsigned char* mlp_lds, int l,
+                                            int64_t el, bool live, const T (&ps)[6], const T (&pc)[21], float qf,
+                                            T chi2, int N, int lane, uint64_t lanes_below, const float4* recs,
+                                            T (&lkey)[Q], int32_t (&lidx)[Q], int32_t (&lslot)[Q], int& cnt,
+                                            int& cnt_in, uint32_t& n_box, uint32_t& n_chi2, uint32_t& n_comp,
+                                            uint32_t& n_fb) {
+  // Window geometry of this lane's candidate (dead lanes only work for others).
+    const float R = p.g.r[l];
+  const LocalPred<T> lp = local_pred(ps, pc);
+  const float px0 = float(ps[0]), py0 = float(ps[1]), pz0 = float(ps[2]);
+  const float rtt = live ? float(lp.att) + p.layer_vmax[2 * el] : 0.f;
+  const float rzz = live ? float(pc[5]) + p.layer_vmax[2 * el + 1] : 0.f;
+  const float fac = 1.f + p.margin;
+  // plain half widths bound the chi2 < cut region (Cauchy-Schwarz on R^-1)
+  const float wt_plain = sqrtf(p.chi2_cut * rtt) * fac;
+  const float wz_plain = sqrtf(p.chi2_cut * rzz) * fac;
+  // Learned window: one network evaluation per live candidate, all lanes of the wave together.  Its box
+  // (never wider than the plain one) decides which compatible hits count; when none is inside it, the
+  // compatible hits of the plain window count instead (fallback).  One scan of the plain window's bins
+  // serves both: pairs inside the learned box are evaluated at once, the other pairs inside the plain box
+  // wait in a second queue.  A candidate with no pair inside its learned box falls back for certain: its
+  // waiting pairs join the last batches of the scan.  One whose inside pairs all fail the cut (rare) takes
+  // them after it.
+  float wt_in = wt_plain, wz_in = wz_plain;
+  bool tighter = false;
+  if (LW) {
+    float f[8];
+    if (live) {
+      window_features(ps, pc, qf, p.g.r[l - 1], R, p.g.z_half[l], f);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) f[k] = 0.f;
+    }
+    float o0, o1;
+    const uint64_t um = __ballot(live);
+    const int lpos = live ? __popcll(um & lanes_below) : -1;
+    wave_lds_sync();
+    if (live) C.live_lane[lpos] = lane;
+    wave_lds_sync();
+    kfm::eval_compact_lds(mlp_lds, f, lane, C.live_lane, __popcll(um), lpos, o0, o1);
+    if (live) {
+      const float lwt = p.nsigma * __expf(o0);
+      const float lwz = p.nsigma * __expf(o1);
+      tighter = lwt < wt_plain || lwz < wz_plain;
+      wt_in = fminf(lwt, wt_plain);
+      wz_in = fminf(lwz, wz_plain);
+    }
+    C.lbox[0][lane] = wt_in;
+    C.lbox[1][lane] = wz_in;
+    C.need[lane] = tighter ? 1 : 0;  // cleared by the first pair inside the learned box
+  }
+  const float php = atan2f(py0, px0);
+  const float emax = asinhf(p.g.z_half[l] / R);
+  const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
+  C.pred[0][lane] = ps[0];
+  C.pred[1][lane] = ps[1];
+  C.pred[2][lane] = ps[2];
+  C.pred[3][lane] = lp.nx;
+  C.pred[4][lane] = lp.ny;
+  C.pred[5][lane] = lp.att;
+  C.pred[6][lane] = lp.atz;
+  C.pred[7][lane] = lp.azz;
+  C.box[0][lane] = wt_plain;
+  C.box[1][lane] = wz_plain;
+  // bins the plain window overlaps: the cyclic phi interval [ip0, ip0 + nspan) and the eta rows ie0..ie1
+  int ip0 = 0, nspan = p.n_phi, ie0 = 0, ie1 = -1;
+  if (live) {
+    const float sphi = wt_plain / R;
+    if (sphi < 1.f) {
+      const float dphi = asinf(sphi);
+      if (dphi < 1.5707963f) {
+        ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
+        const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
+        nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
+      }
+    }
+    ie0 = eta_bin_f(pz0 - wz_plain, R, emax, p.n_eta);
+    ie1 = eta_bin_f(pz0 + wz_plain, R, emax, p.n_eta);
+  }
+  const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
+  const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
+  const int nr = live ? 2 * (ie1 - ie0 + 1) : 0;
+  const int max_nr = wave_max_i(nr);
+  // bounds of this lane's r-th slot range (row ie0 + r/2, segment r%2)
+  auto range_of = [&](int r, int& ra, int& rn) {
+    ra = 0;
+    rn = 0;
+    if (r < nr) {
+      const int row = (ie0 + (r >> 1)) * p.n_phi;
+      if ((r & 1) == 0) {
+        ra = bo[row + ip0];
+        rn = bo[row + first_end] - ra;
+      } else if (wrap_end > 0) {
+        ra = bo[row];
+        rn = bo[row + wrap_end] - ra;
+      }
+    }
+  };
+  int qn = 0;  // pairs awaiting their chi2, carried across the ranges
+  int qb = 0;  // learned window: pairs inside the plain box but outside the learned one, waiting
+  // Evaluates the queue 64 pairs at a time (all of it when final) and inserts the compatible hits into the
+  // owners' lists.  A queued owner with bit 6 set marks a pair outside the learned box: its hit is flagged
+  // (bit 30 of the index) and ranks after every unflagged hit of the list.
+  auto flush = [&](bool final_batch) {
+    while (qn >= 64 || (final_batch && qn > 0)) {
+      wave_lds_sync();
+      const int nb = qn < 64 ? qn : 64;
+      bool comp = false;
+      T c2 = T(0);
+      int32_t hidx = 0, jq = 0, oq = 0;
+      if (lane < nb) {
+        jq = C.q_slot[lane];
+        const int qo = C.q_own[lane];
+        oq = qo & 63;
+        const float4 h = recs[static_cast<int64_t>(jq) * 3];
+        const float4 c0 = recs[static_cast<int64_t>(jq) * 3 + 1];
+        const float4 c1 = recs[static_cast<int64_t>(jq) * 3 + 2];
+        const float mm[3] = {h.x, h.y, h.z};
+        const float vv[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
+        T pos3[6];
+        pos3[0] = C.pred[0][oq];
+        pos3[1] = C.pred[1][oq];
+        pos3[2] = C.pred[2][oq];
+        LocalPred<T> L;
+        L.nx = C.pred[3][oq];
+        L.ny = C.pred[4][oq];
+        L.tx = -L.ny;
+        L.ty = L.nx;
+        L.att = C.pred[5][oq];
+        L.atz = C.pred[6][oq];
+        L.azz = C.pred[7][oq];
+        if (!chi2_on_layer(pos3, L, mm, vv, c2) && c2 < T(p.chi2_cut)) {
+          comp = true;
+          hidx = __float_as_int(h.w) | (LW ? ((qo >> 6) << 30) : 0);
+        }
+      }
+      n_chi2 += nb;
+      n_comp += __popcll(__ballot(comp));
+      // group the compatible results by candidate: per-candidate counts, their prefix, then each
+      // result at its candidate's start plus its rank (the insertion order does not matter: the
+      // top-N list orders by its key)
+      wave_lds_sync();  // queue entries read
+      C.cnt[lane] = 0;
+      wave_lds_sync();
+      const int rank = comp ? atomicAdd(&C.cnt[oq], 1) : 0;
+      wave_lds_sync();
+      const int count = C.cnt[lane];
+      int cinc = count;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(cinc, o);
+        if (lane >= o) cinc += y;
+      }
+      const int first = cinc - count;
+      C.rstart[lane] = first;
+      wave_lds_sync();
+      if (comp) {
+        const int rp = C.rstart[oq] + rank;
+        C.r_idx[rp] = hidx;
+        C.r_slot[rp] = jq;
+        C.r_c2[rp] = c2;
+      }
+      // move the unevaluated rest of the queue to its front
+      const int rest = qn - nb;
+      int keep_s[kScanUnroll + 1], keep_o[kScanUnroll + 1];
+#pragma unroll
+      for (int u = 0; u <= kScanUnroll; ++u) {
+        const int from = nb + 64 * u + lane;
+        keep_s[u] = from < qn ? C.q_slot[from] : 0;
+        keep_o[u] = from < qn ? C.q_own[from] : 0;
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int u = 0; u <= kScanUnroll; ++u) {
+        const int to = 64 * u + lane;
+        if (to < rest) {
+          C.q_slot[to] = keep_s[u];
+          C.q_own[to] = static_cast<uint8_t>(keep_o[u]);
+        }
+      }
+      qn = rest;
+      wave_lds_sync();
+      const int rounds = wave_max_i(count);
+      for (int k = 0; k < rounds; ++k) {
+        if (k < count) {
+          const int e = first + k;
+          const T cc = C.r_c2[e];
+          T nk = chi2 + (cc > T(0) ? cc : T(0));
+          int32_t ni = C.r_idx[e];
+          int32_t nj = C.r_slot[e];
+          if (LW && (ni >> 30) == 0) cnt_in = cnt_in + 1 < N ? cnt_in + 1 : N;
+#pragma unroll
+          for (int t = 0; t < Q; ++t) {
+            bool sw;
+            if (LW) {
+              const int fn = ni >> 30, ft = lidx[t] >> 30;
+              sw = (t < N) && (fn < ft || (fn == ft && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]))));
+            } else {
+              sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
+            }
+            const T tk = lkey[t];
+            const int32_t ti = lidx[t], tj = lslot[t];
+            lkey[t] = sw ? nk : tk;
+            lidx[t] = sw ? ni : ti;
+            lslot[t] = sw ? nj : tj;
+            nk = sw ? tk : nk;
+            ni = sw ? ti : ni;
+            nj = sw ? tj : nj;
+          }
+          cnt = cnt + 1 < N ? cnt + 1 : N;
+        }
+      }
+    }
+  };
+  // Appends the waiting pairs whose owner is marked in C.need to the queue, flagged as outside the learned
+  // box (the queue holds them: at most 63 + kQueueDefer pairs).
+  auto take_waiting = [&]() {
+    wave_lds_sync();
+    for (int b0 = 0; b0 < qb; b0 += 64) {
+      const int i = b0 + lane;
+      int jb = 0, ob = 0;
+      bool take = false;
+      if (i < qb) {
+        jb = C.qb_slot[i];
+        ob = C.qb_own[i];
+        take = C.need[ob] != 0;
+      }
+      const uint64_t mt = __ballot(take);
+      if (take) {
+        const int pos = qn + __popcll(mt & lanes_below);
+        C.q_slot[pos] = jb;
+        C.q_own[pos] = static_cast<uint8_t>(ob | 64);
+      }
+      qn += __popcll(mt);
+    }
+  };
+  // Ranges are taken kRangeChunk per lane at a time: their bounds load together, each lane's ranges are
+  // laid end to end (cumulative counts in LDS) and the lanes' totals end to end, so one flat item space
+  // covers them all.
+  for (int r0 = 0; r0 < max_nr; r0 += kRangeChunk) {
+    int ra[kRangeChunk], rn[kRangeChunk];
+#pragma unroll
+    for (int j = 0; j < kRangeChunk; ++j) range_of(r0 + j, ra[j], rn[j]);
+    wave_lds_sync();  // the previous chunk's readers are done with the tables
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < kRangeChunk; ++j) {
+      C.rcum[j][lane] = mine;
+      C.rst[j][lane] = ra[j];
+      mine += rn[j];
+    }
+    int incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    const int total = __shfl(incl, 63);
+    C.off[lane] = incl - mine;
+    wave_lds_sync();
+    for (int base = 0; base < total; base += 64 * kScanUnroll) {
+      n_box += min(total - base, 64 * kScanUnroll);
+      int own[kScanUnroll], js[kScanUnroll];
+      float4 hv[kScanUnroll];
+#pragma unroll
+      for (int u = 0; u < kScanUnroll; ++u) {
+        const int w = base + 64 * u + lane;
+        const int wc = w < total ? w : total - 1;
+        int lo = 0;  // largest candidate lane whose items start at or before item wc
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+          if (C.off[lo + step] <= wc) lo += step;
+        const int local = wc - C.off[lo];
+        int jr = 0;  // that lane's range holding the item
+#pragma unroll
+        for (int step = kRangeChunk / 2; step > 0; step >>= 1)
+          if (C.rcum[jr + step][lo] <= local) jr += step;
+        own[u] = lo;
+        js[u] = C.rst[jr][lo] + (local - C.rcum[jr][lo]);
+        hv[u] = recs[static_cast<int64_t>(js[u]) * 3];
+      }
+#pragma unroll
+      for (int u = 0; u < kScanUnroll; ++u) {
+        const int w = base + 64 * u + lane;
+        bool in_box = false, out_box = false;
+        if (w < total) {
+          const int o = own[u];
+          // tangent (-ny, nx) at the prediction
+          const float dx = hv[u].x - float(C.pred[0][o]), dy = hv[u].y - float(C.pred[1][o]);
+          const float az = fabsf(hv[u].z - float(C.pred[2][o]));
+          const float at = fabsf(-float(C.pred[4][o]) * dx + float(C.pred[3][o]) * dy);
+          const bool plain_box = at <= C.box[0][o] && az <= C.box[1][o];
+          if (LW) {
+            in_box = at <= C.lbox[0][o] && az <= C.lbox[1][o];
+            out_box = !in_box && plain_box;
+            if (in_box) C.need[o] = 0;
+          } else {
+            in_box = plain_box;
+          }
+        }
+        bool to_q = in_box;
+        int flag = 0;
+        if (LW) {
+          const uint64_t mo = __ballot(out_box);
+          const int no = __popcll(mo);
+          if (qb + no <= kQueueDefer) {
+            if (out_box) {
+              const int pos = qb + __popcll(mo & lanes_below);
+              C.qb_slot[pos] = js[u];
+              C.qb_own[pos] = static_cast<uint8_t>(own[u]);
+            }
+            qb += no;
+          } else {
+            // waiting queue full: evaluate these pairs now, flagged as outside the learned box
+            to_q = in_box || out_box;
+            flag = out_box ? 64 : 0;
+          }
+        }
+        const uint64_t m = __ballot(to_q);
+        if (to_q) {
+          const int pos = qn + __popcll(m & lanes_below);
+          C.q_slot[pos] = js[u];
+          C.q_own[pos] = static_cast<uint8_t>(own[u] | flag);
+        }
+        qn += __popcll(m);
+      }
+      flush(false);  // full batches of 64
+    }
+  }
+  // candidates without any pair inside their learned box fall back for certain: their waiting pairs join the
+  // last batches
+  if (LW && qb > 0) take_waiting();
+  flush(true);
+  if (LW) {
+    const bool need = tighter && cnt_in == 0;
+    n_fb += __popcll(__ballot(need));
+    if (qb > 0) {
+      // the rest of the fallbacks: candidates whose pairs inside the learned box all failed the cut
+      wave_lds_sync();
+      const bool late = need && C.need[lane] == 0;
+      if (__ballot(late) != 0) {
+        wave_lds_sync();
+        C.need[lane] = late ? 1 : 0;
+        take_waiting();
+        flush(true);
+      }
+    }
+    // a candidate with a compatible hit inside its learned box keeps only those (they rank first)
+    if (cnt_in > 0) cnt = cnt_in;
+#pragma unroll
+    for (int t = 0; t < Q; ++t) lidx[t] &= 0x3FFFFFFF;
+  }
 }
 
 template <int G, typename T, bool LW>
@@ -500,6 +869,9 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
   // one ScanLds per wave of the block, in dynamic LDS sized by the launch (blockDim / 64 of them)
   extern __shared__ __align__(16) unsigned char build_lds[];
   ScanLds<T, LW>& C = reinterpret_cast<ScanLds<T, LW>*>(build_lds)[threadIdx.x >> 6];
+  const int n_back = L - p.first_layer;  // layers with a back-pointer
+  int32_t* const back = reinterpret_cast<int32_t*>(build_lds + (blockDim.x >> 6) * sizeof(ScanLds<T, LW>)) +
+                        (threadIdx.x >> 6) * n_back * 64;
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const float4* recs = reinterpret_cast<const float4*>(p.binned);
 
@@ -536,355 +908,8 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
     }
     int cnt = 0;     // children in the list (at most N)
     int cnt_in = 0;  // learned window: those inside the learned box (at most N)
-    {
-      // Window geometry of this lane's candidate (dead lanes only work for others).
-      const bool live = active && pstat == 0;
-      const float R = p.g.r[l];
-      const LocalPred<T> lp = local_pred(ps, pc);
-      const float px0 = float(ps[0]), py0 = float(ps[1]), pz0 = float(ps[2]);
-      const float rtt = live ? float(lp.att) + p.layer_vmax[2 * el] : 0.f;
-      const float rzz = live ? float(pc[5]) + p.layer_vmax[2 * el + 1] : 0.f;
-      const float fac = 1.f + p.margin;
-      // plain half widths bound the chi2 < cut region (Cauchy-Schwarz on R^-1)
-      const float wt_plain = sqrtf(p.chi2_cut * rtt) * fac;
-      const float wz_plain = sqrtf(p.chi2_cut * rzz) * fac;
-      // Learned window: one network evaluation per live candidate, all lanes of the wave together.  Its box
-      // (never wider than the plain one) decides which compatible hits count; when none is inside it, the
-      // compatible hits of the plain window count instead (fallback).  One scan of the plain window's bins
-      // serves both: pairs inside the learned box are evaluated at once, the other pairs inside the plain box
-      // wait in a second queue.  A candidate with no pair inside its learned box falls back for certain: its
-      // waiting pairs join the last batches of the scan.  One whose inside pairs all fail the cut (rare) takes
-      // them after it.
-      float wt_in = wt_plain, wz_in = wz_plain;
-      bool tighter = false;
-      if (LW) {
-        float f[8];
-        if (live) {
-          window_features(ps, pc, qf, p.g.r[l - 1], R, p.g.z_half[l], f);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) f[k] = 0.f;
-        }
-        float o0, o1;
-        const uint64_t um = __ballot(live);
-        const int lpos = live ? __popcll(um & lanes_below) : -1;
-        wave_lds_sync();
-        if (live) C.live_lane[lpos] = lane;
-        wave_lds_sync();
-        kfm::eval_compact_lds(mlp_lds, f, lane, C.live_lane, __popcll(um), lpos, o0, o1);
-        if (live) {
-          const float lwt = p.nsigma * __expf(o0);
-          const float lwz = p.nsigma * __expf(o1);
-          tighter = lwt < wt_plain || lwz < wz_plain;
-          wt_in = fminf(lwt, wt_plain);
-          wz_in = fminf(lwz, wz_plain);
-        }
-        C.lbox[0][lane] = wt_in;
-        C.lbox[1][lane] = wz_in;
-        C.need[lane] = tighter ? 1 : 0;  // cleared by the first pair inside the learned box
-      }
-      const float php = atan2f(py0, px0);
-      const float emax = asinhf(p.g.z_half[l] / R);
-      const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
-      C.pred[0][lane] = ps[0];
-      C.pred[1][lane] = ps[1];
-      C.pred[2][lane] = ps[2];
-      C.pred[3][lane] = lp.nx;
-      C.pred[4][lane] = lp.ny;
-      C.pred[5][lane] = lp.att;
-      C.pred[6][lane] = lp.atz;
-      C.pred[7][lane] = lp.azz;
-      C.box[0][lane] = wt_plain;
-      C.box[1][lane] = wz_plain;
-      // bins the plain window overlaps: the cyclic phi interval [ip0, ip0 + nspan) and the eta rows ie0..ie1
-      int ip0 = 0, nspan = p.n_phi, ie0 = 0, ie1 = -1;
-      if (live) {
-        const float sphi = wt_plain / R;
-        if (sphi < 1.f) {
-          const float dphi = asinf(sphi);
-          if (dphi < 1.5707963f) {
-            ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
-            const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
-            nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
-          }
-        }
-        ie0 = eta_bin_f(pz0 - wz_plain, R, emax, p.n_eta);
-        ie1 = eta_bin_f(pz0 + wz_plain, R, emax, p.n_eta);
-      }
-      const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
-      const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
-      const int nr = live ? 2 * (ie1 - ie0 + 1) : 0;
-      const int max_nr = wave_max_i(nr);
-      // bounds of this lane's r-th slot range (row ie0 + r/2, segment r%2)
-      auto range_of = [&](int r, int& ra, int& rn) {
-        ra = 0;
-        rn = 0;
-        if (r < nr) {
-          const int row = (ie0 + (r >> 1)) * p.n_phi;
-          if ((r & 1) == 0) {
-            ra = bo[row + ip0];
-            rn = bo[row + first_end] - ra;
-          } else if (wrap_end > 0) {
-            ra = bo[row];
-            rn = bo[row + wrap_end] - ra;
-          }
-        }
-      };
-      int qn = 0;  // pairs awaiting their chi2, carried across the ranges
-      int qb = 0;  // learned window: pairs inside the plain box but outside the learned one, waiting
-      // Evaluates the queue 64 pairs at a time (all of it when final) and inserts the compatible hits into the
-      // owners' lists.  A queued owner with bit 6 set marks a pair outside the learned box: its hit is flagged
-      // (bit 30 of the index) and ranks after every unflagged hit of the list.
-      auto flush = [&](bool final_batch) {
-        while (qn >= 64 || (final_batch && qn > 0)) {
-          wave_lds_sync();
-          const int nb = qn < 64 ? qn : 64;
-          bool comp = false;
-          T c2 = T(0);
-          int32_t hidx = 0, jq = 0, oq = 0;
-          if (lane < nb) {
-            jq = C.q_slot[lane];
-            const int qo = C.q_own[lane];
-            oq = qo & 63;
-            const float4 h = recs[static_cast<int64_t>(jq) * 3];
-            const float4 c0 = recs[static_cast<int64_t>(jq) * 3 + 1];
-            const float4 c1 = recs[static_cast<int64_t>(jq) * 3 + 2];
-            const float mm[3] = {h.x, h.y, h.z};
-            const float vv[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
-            T pos3[6];
-            pos3[0] = C.pred[0][oq];
-            pos3[1] = C.pred[1][oq];
-            pos3[2] = C.pred[2][oq];
-            LocalPred<T> L;
-            L.nx = C.pred[3][oq];
-            L.ny = C.pred[4][oq];
-            L.tx = -L.ny;
-            L.ty = L.nx;
-            L.att = C.pred[5][oq];
-            L.atz = C.pred[6][oq];
-            L.azz = C.pred[7][oq];
-            if (!chi2_on_layer(pos3, L, mm, vv, c2) && c2 < T(p.chi2_cut)) {
-              comp = true;
-              hidx = __float_as_int(h.w) | (LW ? ((qo >> 6) << 30) : 0);
-            }
-          }
-          n_chi2 += nb;
-          n_comp += __popcll(__ballot(comp));
-          // group the compatible results by candidate: per-candidate counts, their prefix, then each
-          // result at its candidate's start plus its rank (the insertion order does not matter: the
-          // top-N list orders by its key)
-          wave_lds_sync();  // queue entries read
-          C.cnt[lane] = 0;
-          wave_lds_sync();
-          const int rank = comp ? atomicAdd(&C.cnt[oq], 1) : 0;
-          wave_lds_sync();
-          const int count = C.cnt[lane];
-          int cinc = count;
-#pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(cinc, o);
-            if (lane >= o) cinc += y;
-          }
-          const int first = cinc - count;
-          C.rstart[lane] = first;
-          wave_lds_sync();
-          if (comp) {
-            const int rp = C.rstart[oq] + rank;
-            C.r_idx[rp] = hidx;
-            C.r_slot[rp] = jq;
-            C.r_c2[rp] = c2;
-          }
-          // move the unevaluated rest of the queue to its front
-          const int rest = qn - nb;
-          int keep_s[kScanUnroll + 1], keep_o[kScanUnroll + 1];
-#pragma unroll
-          for (int u = 0; u <= kScanUnroll; ++u) {
-            const int from = nb + 64 * u + lane;
-            keep_s[u] = from < qn ? C.q_slot[from] : 0;
-            keep_o[u] = from < qn ? C.q_own[from] : 0;
-          }
-          wave_lds_sync();
-#pragma unroll
-          for (int u = 0; u <= kScanUnroll; ++u) {
-            const int to = 64 * u + lane;
-            if (to < rest) {
-              C.q_slot[to] = keep_s[u];
-              C.q_own[to] = static_cast<uint8_t>(keep_o[u]);
-            }
-          }
-          qn = rest;
-          wave_lds_sync();
-          const int rounds = wave_max_i(count);
-          for (int k = 0; k < rounds; ++k) {
-            if (k < count) {
-              const int e = first + k;
-              const T cc = C.r_c2[e];
-              T nk = chi2 + (cc > T(0) ? cc : T(0));
-              int32_t ni = C.r_idx[e];
-              int32_t nj = C.r_slot[e];
-              if (LW && (ni >> 30) == 0) cnt_in = cnt_in + 1 < N ? cnt_in + 1 : N;
-#pragma unroll
-              for (int t = 0; t < G; ++t) {
-                bool sw;
-                if (LW) {
-                  const int fn = ni >> 30, ft = lidx[t] >> 30;
-                  sw = (t < N) && (fn < ft || (fn == ft && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]))));
-                } else {
-                  sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
-                }
-                const T tk = lkey[t];
-                const int32_t ti = lidx[t], tj = lslot[t];
-                lkey[t] = sw ? nk : tk;
-                lidx[t] = sw ? ni : ti;
-                lslot[t] = sw ? nj : tj;
-                nk = sw ? tk : nk;
-                ni = sw ? ti : ni;
-                nj = sw ? tj : nj;
-              }
-              cnt = cnt + 1 < N ? cnt + 1 : N;
-            }
-          }
-        }
-      };
-      // Appends the waiting pairs whose owner is marked in C.need to the queue, flagged as outside the learned
-      // box (the queue holds them: at most 63 + kQueueDefer pairs).
-      auto take_waiting = [&]() {
-        wave_lds_sync();
-        for (int b0 = 0; b0 < qb; b0 += 64) {
-          const int i = b0 + lane;
-          int jb = 0, ob = 0;
-          bool take = false;
-          if (i < qb) {
-            jb = C.qb_slot[i];
-            ob = C.qb_own[i];
-            take = C.need[ob] != 0;
-          }
-          const uint64_t mt = __ballot(take);
-          if (take) {
-            const int pos = qn + __popcll(mt & lanes_below);
-            C.q_slot[pos] = jb;
-            C.q_own[pos] = static_cast<uint8_t>(ob | 64);
-          }
-          qn += __popcll(mt);
-        }
-      };
-      // Ranges are taken kRangeChunk per lane at a time: their bounds load together, each lane's ranges are
-      // laid end to end (cumulative counts in LDS) and the lanes' totals end to end, so one flat item space
-      // covers them all.
-      for (int r0 = 0; r0 < max_nr; r0 += kRangeChunk) {
-        int ra[kRangeChunk], rn[kRangeChunk];
-#pragma unroll
-        for (int j = 0; j < kRangeChunk; ++j) range_of(r0 + j, ra[j], rn[j]);
-        wave_lds_sync();  // the previous chunk's readers are done with the tables
-        int mine = 0;
-#pragma unroll
-        for (int j = 0; j < kRangeChunk; ++j) {
-          C.rcum[j][lane] = mine;
-          C.rst[j][lane] = ra[j];
-          mine += rn[j];
-        }
-        int incl = mine;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int y = __shfl_up(incl, o);
-          if (lane >= o) incl += y;
-        }
-        const int total = __shfl(incl, 63);
-        C.off[lane] = incl - mine;
-        wave_lds_sync();
-        for (int base = 0; base < total; base += 64 * kScanUnroll) {
-          n_box += min(total - base, 64 * kScanUnroll);
-          int own[kScanUnroll], js[kScanUnroll];
-          float4 hv[kScanUnroll];
-#pragma unroll
-          for (int u = 0; u < kScanUnroll; ++u) {
-            const int w = base + 64 * u + lane;
-            const int wc = w < total ? w : total - 1;
-            int lo = 0;  // largest candidate lane whose items start at or before item wc
-#pragma unroll
-            for (int step = 32; step > 0; step >>= 1)
-              if (C.off[lo + step] <= wc) lo += step;
-            const int local = wc - C.off[lo];
-            int jr = 0;  // that lane's range holding the item
-#pragma unroll
-            for (int step = kRangeChunk / 2; step > 0; step >>= 1)
-              if (C.rcum[jr + step][lo] <= local) jr += step;
-            own[u] = lo;
-            js[u] = C.rst[jr][lo] + (local - C.rcum[jr][lo]);
-            hv[u] = recs[static_cast<int64_t>(js[u]) * 3];
-          }
-#pragma unroll
-          for (int u = 0; u < kScanUnroll; ++u) {
-            const int w = base + 64 * u + lane;
-            bool in_box = false, out_box = false;
-            if (w < total) {
-              const int o = own[u];
-              // tangent (-ny, nx) at the prediction
-              const float dx = hv[u].x - float(C.pred[0][o]), dy = hv[u].y - float(C.pred[1][o]);
-              const float az = fabsf(hv[u].z - float(C.pred[2][o]));
-              const float at = fabsf(-float(C.pred[4][o]) * dx + float(C.pred[3][o]) * dy);
-              const bool plain_box = at <= C.box[0][o] && az <= C.box[1][o];
-              if (LW) {
-                in_box = at <= C.lbox[0][o] && az <= C.lbox[1][o];
-                out_box = !in_box && plain_box;
-                if (in_box) C.need[o] = 0;
-              } else {
-                in_box = plain_box;
-              }
-            }
-            bool to_q = in_box;
-            int flag = 0;
-            if (LW) {
-              const uint64_t mo = __ballot(out_box);
-              const int no = __popcll(mo);
-              if (qb + no <= kQueueDefer) {
-                if (out_box) {
-                  const int pos = qb + __popcll(mo & lanes_below);
-                  C.qb_slot[pos] = js[u];
-                  C.qb_own[pos] = static_cast<uint8_t>(own[u]);
-                }
-                qb += no;
-              } else {
-                // waiting queue full: evaluate these pairs now, flagged as outside the learned box
-                to_q = in_box || out_box;
-                flag = out_box ? 64 : 0;
-              }
-            }
-            const uint64_t m = __ballot(to_q);
-            if (to_q) {
-              const int pos = qn + __popcll(m & lanes_below);
-              C.q_slot[pos] = js[u];
-              C.q_own[pos] = static_cast<uint8_t>(own[u] | flag);
-            }
-            qn += __popcll(m);
-          }
-          flush(false);  // full batches of 64
-        }
-      }
-      // candidates without any pair inside their learned box fall back for certain: their waiting pairs join the
-      // last batches
-      if (LW && qb > 0) take_waiting();
-      flush(true);
-      if (LW) {
-        const bool need = tighter && cnt_in == 0;
-        n_fb += __popcll(__ballot(need));
-        if (qb > 0) {
-          // the rest of the fallbacks: candidates whose pairs inside the learned box all failed the cut
-          wave_lds_sync();
-          const bool late = need && C.need[lane] == 0;
-          if (__ballot(late) != 0) {
-            wave_lds_sync();
-            C.need[lane] = late ? 1 : 0;
-            take_waiting();
-            flush(true);
-          }
-        }
-        // a candidate with a compatible hit inside its learned box keeps only those (they rank first)
-        if (cnt_in > 0) cnt = cnt_in;
-#pragma unroll
-        for (int t = 0; t < G; ++t) lidx[t] &= 0x3FFFFFFF;
-      }
-    }
+    scan_window<G, T, LW>(p, C, mlp_lds, l, el, active && pstat == 0, ps, pc, qf, chi2, N, lane, lanes_below, recs,
+                          lkey, lidx, lslot, cnt, cnt_in, n_box, n_chi2, n_comp, n_fb);
     // ---- merge the seed's lists: N rounds of a G-lane minimum of the rank key
     bool hole_left = active;
     uint64_t mine = ~0ull;  // the child that becomes this slot's candidate
@@ -948,8 +973,11 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
         const int32_t r = update_on_layer<T, double>(st, cv, m, v, dc2);
         if (r) status = r;
       }
-      p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + slot] =
-          static_cast<int32_t>((static_cast<uint32_t>(key_parent(mine)) << 24) | hid);
+      const int32_t rec = static_cast<int32_t>((static_cast<uint32_t>(key_parent(mine)) << 24) | hid);
+      if (kBackLds<LW>)
+        back[(l - p.first_layer) * 64 + lane] = rec;
+      else
+        p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + slot] = rec;
     }
     nc = new_nc;
   }
@@ -969,15 +997,18 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       for (int k = 0; k < 21; ++k) p.best_cov[k * p.ld_seed + s] = static_cast<float>(cv[k]);
     }
   }
-  // backtrack the parent chain in place: at each layer every lane reads its
-  // record before any lane of the wave writes that layer (data dependence)
+  // backtrack the parent chain (from LDS, or in place in cand_hits: at each layer every lane reads its
+  // record before any lane of the wave writes that layer, a data dependence)
   int kk = slot;
   const bool live = seed_ok && slot < nc;
+  if (kBackLds<LW>) wave_lds_sync();
   for (int l = L - 1; l >= p.first_layer; --l) {
     int32_t out = -1;
     int64_t at = static_cast<int64_t>(l) * p.n_seeds * N + s * N + slot;
     if (live) {
-      const uint32_t rec = static_cast<uint32_t>(p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + kk]);
+      const uint32_t rec =
+          kBackLds<LW> ? static_cast<uint32_t>(back[(l - p.first_layer) * 64 + gbase + kk])
+                       : static_cast<uint32_t>(p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + kk]);
       const uint32_t hid = rec & kHole;
       kk = static_cast<int>(rec >> 24);
       out = (hid == kHole) ? -1 : static_cast<int32_t>(p.layer_offsets[static_cast<int64_t>(ev) * L + l] + hid);
@@ -998,6 +1029,293 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
     for (int i = 0; i < KF_BUILD_COUNTERS; ++i)
       if (v[i]) atomicAdd(&p.counters[i], static_cast<unsigned long long>(v[i]));
   }
+}
+
+// ---------------------------------------------------------------------------
+// Serial-candidate building: one lane per seed (64 seeds a wave) holding all
+// of its candidates, which it takes one after the other (the paper's proposed
+// one thread per seed).  A candidate's state, covariance and (hits, chi2,
+// status) live in a device buffer indexed by tile position, so that the loads
+// of a wave are coalesced: buffer A holds the layer's candidates (overwritten
+// by their propagated states), buffer B the survivors.  For every candidate
+// index c the wave propagates and scans the c-th candidate of each of its
+// seeds together (the same wave-cooperative scan as the grouped build), and
+// each lane merges the children into its seed's top-N list in registers.
+// Results are those of the grouped build: same rank key, same order of keys.
+// ---------------------------------------------------------------------------
+constexpr int kSerialWords = 30;  // 6 state + 21 covariance + nhits, chi2, status (as float bits)
+
+__device__ __forceinline__ uint64_t sel_key(const uint64_t (&k)[kSerialMax], int r) {
+  uint64_t v = k[0];
+#pragma unroll
+  for (int t = 1; t < kSerialMax; ++t) v = (r == t) ? k[t] : v;
+  return v;
+}
+__device__ __forceinline__ int32_t sel_i32(const int32_t (&k)[kSerialMax], int r) {
+  int32_t v = k[0];
+#pragma unroll
+  for (int t = 1; t < kSerialMax; ++t) v = (r == t) ? k[t] : v;
+  return v;
+}
+__device__ __forceinline__ float sel_f(const float (&k)[kSerialMax], int r) {
+  float v = k[0];
+#pragma unroll
+  for (int t = 1; t < kSerialMax; ++t) v = (r == t) ? k[t] : v;
+  return v;
+}
+
+__device__ void build_serial_tile(const BuildP& p, int64_t tile) {
+  using T = float;
+  const int lane = threadIdx.x & 63;
+  const int64_t pos = tile * 64 + lane;
+  const bool seed_ok = pos < p.n_seeds;
+  const int64_t s = (seed_ok && p.order) ? static_cast<int64_t>(p.order[pos]) : pos;
+  const int L = p.g.n_layers;
+  const int N = p.max_cands;
+  int ev = 0;
+  if (seed_ok) {
+    int lo = 0, hi = p.n_events;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (p.seed_offsets[mid] <= s) lo = mid; else hi = mid;
+    }
+    ev = lo;
+  }
+  const T a = T(-static_cast<double>(seed_ok ? p.seed_charge[s] : 1) * kCLight * p.g.bz);
+  const float qf = seed_ok ? static_cast<float>(p.seed_charge[s]) : 1.f;
+  const int64_t ld = p.buf_ld;
+  const int64_t bstride = static_cast<int64_t>(kSerialWords) * N * ld;  // one buffer
+  // word k of candidate c in buffer b
+  auto at = [&](int b, int c, int k) -> float& { return p.cand_buf[b * bstride + (static_cast<int64_t>(k) * N + c) * ld + pos]; };
+  int cur = 0;
+  int nc = seed_ok ? 1 : 0;
+  if (seed_ok) {
+    T st[6], cv[21];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) st[k] = T(p.seed_state[k * p.ld_seed + s]);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) cv[k] = T(p.seed_cov[k * p.ld_seed + s]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) at(cur, 0, k) = st[k];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) at(cur, 0, 6 + k) = cv[k];
+    at(cur, 0, 27) = __int_as_float(3);
+    at(cur, 0, 28) = 0.f;
+    at(cur, 0, 29) = __int_as_float(finite6_21(st, cv) ? 0 : ST_NONFINITE);
+  }
+  uint32_t n_box = 0, n_chi2 = 0, n_comp = 0, n_steps = 0, n_upd = 0, n_fb = 0;
+  extern __shared__ __align__(16) unsigned char build_lds[];
+  ScanLds<T, false>& C = reinterpret_cast<ScanLds<T, false>*>(build_lds)[threadIdx.x >> 6];
+  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const float4* recs = reinterpret_cast<const float4*>(p.binned);
+
+  for (int l = p.first_layer; l < L; ++l) {
+    const int64_t el = static_cast<int64_t>(ev) * L + l;
+    // the seed's best N children over all of its candidates: rank keys, slots, accumulated chi2
+    uint64_t skey[kSerialMax];
+    int32_t sslot[kSerialMax];
+    float sc2[kSerialMax];
+#pragma unroll
+    for (int t = 0; t < kSerialMax; ++t) {
+      skey[t] = ~0ull;
+      sslot[t] = -1;
+      sc2[t] = 0.f;
+    }
+    const int max_nc = wave_max_i(nc);
+#pragma unroll 1
+    for (int c = 0; c < max_nc; ++c) {
+      const bool active = c < nc;
+      T ps[6], pc[21];
+      int nhits = 0;
+      T chi2 = T(0);
+      int32_t status = 0;
+      if (active) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ps[k] = at(cur, c, k);
+#pragma unroll
+        for (int k = 0; k < 21; ++k) pc[k] = at(cur, c, 6 + k);
+        nhits = __float_as_int(at(cur, c, 27));
+        chi2 = at(cur, c, 28);
+        status = __float_as_int(at(cur, c, 29));
+      } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ps[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < 21; ++k) pc[k] = T(0);
+      }
+      // propagate (material of the layer the candidate sits on, then the crossing); a failing step keeps the
+      // state before it and the candidate is carried unchanged
+      int32_t pstat = status;
+      n_steps += __popcll(__ballot(active && status == 0));
+      if (active && status == 0) {
+        T ss[6], sv[21];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ss[k] = ps[k];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) sv[k] = pc[k];
+        int32_t r = material(ps, pc, T(p.g.x_over_x0[l - 1]), T(p.g.eloss_per_x0), T(p.g.mass));
+        if (!r) r = propagate(ps, pc, a, T(p.g.r[l]), T(p.g.z_half[l]));
+        if (r) {
+          pstat = r;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) ps[k] = ss[k];
+#pragma unroll
+          for (int k = 0; k < 21; ++k) pc[k] = sv[k];
+        }
+      }
+      if (active) {  // the propagated state replaces the candidate's (the survivors start from it)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) at(cur, c, k) = ps[k];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) at(cur, c, 6 + k) = pc[k];
+        at(cur, c, 29) = __int_as_float(pstat);
+      }
+      T lkey[kSerialMax];
+      int32_t lidx[kSerialMax], lslot[kSerialMax];
+#pragma unroll
+      for (int t = 0; t < kSerialMax; ++t) {
+        lkey[t] = T(INFINITY);
+        lidx[t] = 0x7FFFFFFF;
+        lslot[t] = 0;
+      }
+      int cnt = 0, cnt_in = 0;
+      scan_window<kSerialMax, T, false>(p, C, nullptr, l, el, active && pstat == 0, ps, pc, qf, chi2, N, lane,
+                                        lanes_below, recs, lkey, lidx, lslot, cnt, cnt_in, n_box, n_chi2, n_comp,
+                                        n_fb);
+      // the candidate's children into the seed's list: its compatible hits (if it was propagated), else or
+      // besides them its hole child
+      if (active) {
+#pragma unroll
+        for (int t = 0; t <= kSerialMax; ++t) {
+          uint64_t nk;
+          int32_t nj;
+          float nc2;
+          if (t < kSerialMax) {
+            if (!(pstat == 0 && t < cnt)) continue;
+            nk = make_key(nhits + 1, float(lkey[t]), c, static_cast<uint32_t>(lidx[t]));
+            nj = lslot[t];
+            nc2 = float(lkey[t]);
+          } else {
+            nk = make_key(nhits, float(chi2), c, kHole);
+            nj = -1;
+            nc2 = float(chi2);
+          }
+#pragma unroll
+          for (int u = 0; u < kSerialMax; ++u) {
+            const bool sw = u < N && nk < skey[u];
+            const uint64_t tk = skey[u];
+            const int32_t tj = sslot[u];
+            const float tc = sc2[u];
+            skey[u] = sw ? nk : tk;
+            sslot[u] = sw ? nj : tj;
+            sc2[u] = sw ? nc2 : tc;
+            nk = sw ? tk : nk;
+            nj = sw ? tj : nj;
+            nc2 = sw ? tc : nc2;
+          }
+        }
+      }
+    }
+    // the survivors: each starts from its parent's propagated state and, with a hit, is updated (clone engine)
+    int new_nc = 0;
+#pragma unroll
+    for (int t = 0; t < kSerialMax; ++t) new_nc += (t < N && skey[t] != ~0ull) ? 1 : 0;
+    const int nxt = cur ^ 1;
+    const int max_new = wave_max_i(new_nc);
+#pragma unroll 1
+    for (int r = 0; r < max_new; ++r) {
+      const bool on = r < new_nc;
+      const uint64_t k = sel_key(skey, r);
+      const int par = on ? key_parent(k) : 0;
+      const uint32_t hid = key_hit(k);
+      T st[6], cv[21];
+      int32_t status = 0;
+      if (on) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) st[q] = at(cur, par, q);
+#pragma unroll
+        for (int q = 0; q < 21; ++q) cv[q] = at(cur, par, 6 + q);
+        status = __float_as_int(at(cur, par, 29));
+      }
+      n_upd += __popcll(__ballot(on && hid != kHole && status == 0));
+      if (on && hid != kHole && status == 0) {
+        const int32_t sl = sel_i32(sslot, r);
+        const float4 h = recs[static_cast<int64_t>(sl) * 3];
+        const float4 c0 = recs[static_cast<int64_t>(sl) * 3 + 1];
+        const float4 c1 = recs[static_cast<int64_t>(sl) * 3 + 2];
+        const float m[3] = {h.x, h.y, h.z};
+        const float v[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
+        T dc2;
+        const int32_t rr = update_on_layer<T, double>(st, cv, m, v, dc2);
+        if (rr) status = rr;
+      }
+      if (on) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) at(nxt, r, q) = st[q];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) at(nxt, r, 6 + q) = cv[q];
+        at(nxt, r, 27) = __int_as_float(key_nhits(k));
+        at(nxt, r, 28) = sel_f(sc2, r);
+        at(nxt, r, 29) = __int_as_float(status);
+        p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + r] =
+            static_cast<int32_t>((static_cast<uint32_t>(par) << 24) | hid);
+      }
+    }
+    nc = new_nc;
+    cur = nxt;
+  }
+  // ---- outputs
+  if (seed_ok) {
+    p.n_cands[s] = nc;
+    for (int r = 0; r < N; ++r) {
+      const bool live = r < nc;
+      p.cand_chi2[s * N + r] = live ? at(cur, r, 28) : 0.f;
+      p.cand_nhits[s * N + r] = live ? __float_as_int(at(cur, r, 27)) : 0;
+      p.cand_status[s * N + r] = live ? __float_as_int(at(cur, r, 29)) : 0;
+    }
+    if (p.best_state) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) p.best_state[k * p.ld_seed + s] = at(cur, 0, k);
+#pragma unroll
+      for (int k = 0; k < 21; ++k) p.best_cov[k * p.ld_seed + s] = at(cur, 0, 6 + k);
+    }
+    // backtrack each final candidate's parent chain: one lane holds all of the seed's chains, so it reads a
+    // layer's records before it rewrites them
+    int32_t kk[kSerialMax];
+#pragma unroll
+    for (int r = 0; r < kSerialMax; ++r) kk[r] = r;
+    for (int l = L - 1; l >= p.first_layer; --l) {
+      int32_t* row = p.cand_hits + static_cast<int64_t>(l) * p.n_seeds * N + s * N;
+      int32_t out[kSerialMax];
+#pragma unroll
+      for (int r = 0; r < kSerialMax; ++r) {
+        out[r] = -1;
+        if (r < nc) {
+          const uint32_t rec = static_cast<uint32_t>(row[kk[r]]);
+          const uint32_t hid = rec & kHole;
+          kk[r] = static_cast<int>(rec >> 24);
+          out[r] = (hid == kHole) ? -1 : static_cast<int32_t>(p.layer_offsets[static_cast<int64_t>(ev) * L + l] + hid);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kSerialMax; ++r)
+        if (r < N) row[r] = out[r];
+    }
+    for (int l = 0; l < p.first_layer; ++l)
+      for (int r = 0; r < N; ++r)
+        p.cand_hits[static_cast<int64_t>(l) * p.n_seeds * N + s * N + r] =
+            (r < nc && l < 3) ? p.seed_hits[l * p.ld_seed + s] : -1;
+  }
+  if (p.counters && lane == 0) {
+    const uint32_t v[KF_BUILD_COUNTERS] = {n_box, n_chi2, n_comp, n_steps, n_upd, n_fb};
+#pragma unroll
+    for (int i = 0; i < KF_BUILD_COUNTERS; ++i)
+      if (v[i]) atomicAdd(&p.counters[i], static_cast<unsigned long long>(v[i]));
+  }
+}
+
+__global__ void __launch_bounds__(256) build_serial_kernel(BuildP p) {
+  build_serial_tile(p, static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 // forward weights of the window network, staged once per block (learned-window kernels only)
@@ -1190,11 +1508,12 @@ struct Launch {
   unsigned grid, block;
   hipStream_t stream;
   int64_t n_tiles;
+  int n_back;  // layers with a back-pointer (n_layers - first_layer)
 };
 
 template <int G, typename T, bool LW>
 void launch_build(const Launch& c, const BuildP& p) {
-  const size_t lds = (c.block / 64) * sizeof(ScanLds<T, LW>);
+  const size_t lds = (c.block / 64) * (sizeof(ScanLds<T, LW>) + (kBackLds<LW> ? c.n_back * 64 * sizeof(int32_t) : 0));
   if constexpr (std::is_same<T, float>::value) {
     if (c.persistent)
       build_persistent_kernel<G, LW><<<c.grid, c.block, lds, c.stream>>>(p, c.n_tiles);
@@ -1290,6 +1609,12 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
 namespace {
 constexpr size_t kQueueBytes = 256;
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+// serial-candidate build: the two candidate buffers, one slot per tile position (tiles of 64 seeds)
+size_t serial_buf_bytes(const kf_build_cfg* cfg, int64_t n_seeds) {
+  const int64_t ld = (n_seeds + 63) / 64 * 64;
+  const int n = cfg->max_cands >= 1 && cfg->max_cands <= 8 ? cfg->max_cands : 8;
+  return align256(static_cast<size_t>(2) * kSerialWords * n * ld * sizeof(float));
+}
 size_t cells_bytes(int64_t n_events) { return align256(static_cast<size_t>(n_events) * kSeedCells * 4); }
 }  // namespace
 
@@ -1298,6 +1623,7 @@ size_t kf_build_workspace_size(const kf_build_cfg* cfg, int64_t n_events, int64_
   size_t b = kQueueBytes;  // persistent work queue (kept in every layout)
   if (cfg->seed_order)
     b += cells_bytes(n_events) + align256(static_cast<size_t>(n_seeds) * 4) + align256(static_cast<size_t>(n_events) * 8);
+  if (cfg->mode == KF_BUILD_SERIAL) return b + serial_buf_bytes(cfg, n_seeds);
   return (cfg->mode == KF_BUILD_PERSISTENT || cfg->seed_order) ? b : 0;
 }
 
@@ -1359,8 +1685,10 @@ int32_t build_impl(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a,
   if (cfg->n_phi < 1 || cfg->n_eta < 1 || static_cast<int64_t>(cfg->n_phi) * cfg->n_eta > kMaxBinsFine)
     return set_error(KF_ERR_INVALID_ARG, "bad bin counts");
   if (!(cfg->window_margin >= 0.f)) return set_error(KF_ERR_INVALID_ARG, "window_margin must be >= 0");
-  if (cfg->mode != KF_BUILD_TILED && cfg->mode != KF_BUILD_PERSISTENT)
+  if (cfg->mode != KF_BUILD_TILED && cfg->mode != KF_BUILD_PERSISTENT && cfg->mode != KF_BUILD_SERIAL)
     return set_error(KF_ERR_INVALID_ARG, "unknown mode %d", cfg->mode);
+  if (cfg->mode == KF_BUILD_SERIAL && (cfg->window_mode != KF_WINDOW_PLAIN || cfg->precision != KF_PREC_F32))
+    return set_error(KF_ERR_UNSUPPORTED, "the serial-candidate build supports the plain window in single precision");
   if (cfg->window_mode != KF_WINDOW_PLAIN && cfg->window_mode != KF_WINDOW_LEARNED)
     return set_error(KF_ERR_INVALID_ARG, "unknown window mode %d", cfg->window_mode);
   if (cfg->window_mode == KF_WINDOW_LEARNED) {
@@ -1411,6 +1739,8 @@ int32_t build_impl(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a,
   p.best_cov = a->best_cov;
   p.counters = reinterpret_cast<unsigned long long*>(a->counters);
   p.queue = nullptr;
+  p.cand_buf = nullptr;
+  p.buf_ld = 0;
   p.mlp = cfg->window_mode == KF_WINDOW_LEARNED ? static_cast<const unsigned char*>(a->mlp_packed) : nullptr;
   p.nsigma = cfg->learned_nsigma;
   p.g = ctx->dgeom;
@@ -1443,12 +1773,21 @@ int32_t build_impl(kf_ctx* ctx, const kf_build_cfg* cfg, const kf_build_args* a,
     if (int32_t rc = kfh::check_hip(hipGetLastError(), "seed ordering launch")) return rc;
     p.order = order;
   }
+  if (cfg->mode == KF_BUILD_SERIAL) {
+    const int64_t tiles64 = (a->n_seeds + 63) / 64;
+    p.buf_ld = tiles64 * 64;
+    p.cand_buf = reinterpret_cast<float*>(static_cast<unsigned char*>(workspace) + need - serial_buf_bytes(cfg, a->n_seeds));
+    const size_t lds = static_cast<size_t>(wpb) * sizeof(ScanLds<float, false>);
+    build_serial_kernel<<<static_cast<unsigned>((tiles64 + wpb - 1) / wpb), 64u * wpb, lds, stream>>>(p);
+    return kfh::check_hip(hipGetLastError(), "build_serial_kernel launch");
+  }
   const bool f64 = cfg->precision == KF_PREC_F64;
   Launch lc;
   lc.f64 = f64;
   lc.learned = p.mlp != nullptr;
   lc.stream = stream;
   lc.n_tiles = n_tiles;
+  lc.n_back = L - a->first_layer;
   lc.block = 64u * wpb;
   if (cfg->mode == KF_BUILD_TILED) {
     lc.persistent = false;

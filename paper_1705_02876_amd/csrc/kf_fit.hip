@@ -521,7 +521,10 @@ int32_t kf_ctx_create(kf_ctx** out, int32_t device) {
   return KF_OK;
 }
 
-void kf_ctx_destroy(kf_ctx* ctx) { delete ctx; }
+void kf_ctx_destroy(kf_ctx* ctx) {
+  kfh::ctx_release(ctx);
+  delete ctx;
+}
 
 int32_t kf_set_geometry(kf_ctx* ctx, const kf_geometry* g) {
   if (!ctx || !g) return set_error(KF_ERR_INVALID_ARG, "null argument");

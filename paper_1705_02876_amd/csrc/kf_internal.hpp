@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <map>
 #include <string>
+#include <vector>
 
 #include "../../include/kfmi.h"
 #include "kf_device.hpp"
@@ -34,6 +35,9 @@ struct kf_ctx {
   std::map<std::string, kf_tuned> fit_tuned;  // fit launches: waves_per_block holds the block size in waves
   void* scratch = nullptr;                    // device address of this device's static build scratch
   size_t scratch_bytes = 0;
+  hipStream_t pipe[4] = {nullptr, nullptr, nullptr, nullptr};  // kf_build_host: input copies, output copies, and
+                                                               // two kernel streams
+  std::vector<hipEvent_t> pipe_events;                 // kf_build_host: start, then three per chunk
 };
 
 namespace kfh {
@@ -49,6 +53,12 @@ inline int32_t check_hip(hipError_t e, const char* what) {
 int32_t enter(kf_ctx* ctx);
 
 inline hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Creates kf_build_host's four streams (once) and at least n_events timing-free events in ctx.
+int32_t pipe_streams(kf_ctx* ctx, int n_events);
+
+// Releases the streams and events a context created.
+void ctx_release(kf_ctx* ctx);
 
 // Looks up the device address of the static build scratch on ctx's (current) device.
 int32_t scratch_init(kf_ctx* ctx);

@@ -33,6 +33,32 @@ std::string tune_key(const kf_ctx* ctx, const kf_build_cfg* cfg, int64_t n_seeds
 
 }  // namespace
 
+int32_t kfh::pipe_streams(kf_ctx* ctx, int n_events) {
+  for (int i = 0; i < 4; ++i)
+    if (!ctx->pipe[i])  // default priority, not synchronising with the null stream
+      if (int32_t rc = check_hip(hipStreamCreateWithFlags(&ctx->pipe[i], hipStreamNonBlocking), "hipStreamCreate"))
+        return rc;
+  while (static_cast<int>(ctx->pipe_events.size()) < n_events) {
+    hipEvent_t e = nullptr;
+    if (int32_t rc = check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate")) return rc;
+    ctx->pipe_events.push_back(e);
+  }
+  return KF_OK;
+}
+
+void kfh::ctx_release(kf_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  for (int i = 0; i < 4; ++i)
+    if (ctx->pipe[i]) {
+      (void)hipStreamSynchronize(ctx->pipe[i]);
+      (void)hipStreamDestroy(ctx->pipe[i]);
+      ctx->pipe[i] = nullptr;
+    }
+  for (hipEvent_t e : ctx->pipe_events) (void)hipEventDestroy(e);
+  ctx->pipe_events.clear();
+}
+
 std::string kfh::fit_tune_key(const kf_ctx* ctx, uint32_t flags, int64_t n) {
   int bucket = 0;
   while ((int64_t(1) << (bucket + 1)) <= n && bucket < 62) ++bucket;
@@ -111,11 +137,16 @@ int32_t kf_build_autotune(kf_ctx* ctx, kf_build_cfg* cfg, const kf_build_args* a
   kf_build_cfg pc = *cfg;
   pc.mode = KF_BUILD_PERSISTENT;
   const bool can_persist = a.workspace && a.workspace_bytes >= kf_build_workspace_size(&pc, a.n_events, a.n_seeds);
+  kf_build_cfg sc = *cfg;
+  sc.mode = KF_BUILD_SERIAL;
+  const bool can_serial = cfg->window_mode == KF_WINDOW_PLAIN && cfg->precision == KF_PREC_F32 && a.workspace &&
+                          a.workspace_bytes >= kf_build_workspace_size(&sc, a.n_events, a.n_seeds);
   const int wpbs[3] = {1, 2, 4};
   const int bpcs[4] = {1, 2, 4, 8};
   int32_t rc = KF_OK;
-  for (int mode = KF_BUILD_TILED; mode <= KF_BUILD_PERSISTENT && rc == KF_OK; ++mode) {
+  for (int mode = KF_BUILD_TILED; mode <= KF_BUILD_SERIAL && rc == KF_OK; ++mode) {
     if (mode == KF_BUILD_PERSISTENT && !can_persist) continue;
+    if (mode == KF_BUILD_SERIAL && !can_serial) continue;
     for (int wi = 0; wi < 3 && rc == KF_OK; ++wi)
       for (int bi = 0; bi < (mode == KF_BUILD_PERSISTENT ? 4 : 1) && rc == KF_OK; ++bi) {
         kf_build_cfg c = *cfg;
@@ -245,7 +276,8 @@ int32_t kf_autotune_load(kf_ctx* ctx, const char* path) {
     }
     if (std::sscanf(line, " {\"key\": \"%160[^\"]\", \"mode\": %d, \"waves_per_block\": %d, \"blocks_per_cu\": %d, \"ms\": %lf",
                     key, &t.mode, &t.waves_per_block, &t.blocks_per_cu, &ms) != 5 ||
-        (t.mode != KF_BUILD_TILED && t.mode != KF_BUILD_PERSISTENT) || t.waves_per_block < 1 ||
+        (t.mode != KF_BUILD_TILED && t.mode != KF_BUILD_PERSISTENT && t.mode != KF_BUILD_SERIAL) ||
+        t.waves_per_block < 1 ||
         t.waves_per_block > 4 || t.blocks_per_cu < 0 || t.blocks_per_cu > 64) {
       rc = set_error(KF_ERR_INVALID_ARG, "malformed autotune entry in %s", path);
       break;

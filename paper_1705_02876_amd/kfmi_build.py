@@ -4,7 +4,7 @@ from __future__ import annotations
 import ctypes as C
 
 BINNED_FLOATS = 12
-BUILD_TILED, BUILD_PERSISTENT = 0, 1
+BUILD_TILED, BUILD_PERSISTENT, BUILD_SERIAL = 0, 1, 2
 WINDOW_PLAIN, WINDOW_LEARNED = 0, 1
 PREC_F32, PREC_F64 = 0, 1
 BUILD_COUNTERS = 6  # box tests, chi2 evaluations, compatible hits, candidate-layer steps, updates, fallbacks
@@ -53,6 +53,10 @@ def declare(lib):
     lib.kf_build.argtypes = [P, P, P]
     lib.kf_build_noalloc.restype = I32
     lib.kf_build_noalloc.argtypes = [P, P, P]
+    lib.kf_build_host_workspace_size.restype = C.c_size_t
+    lib.kf_build_host_workspace_size.argtypes = [P, P, P]
+    lib.kf_build_host.restype = I32
+    lib.kf_build_host.argtypes = [P, P, P]
     lib.kf_graph_begin.restype = I32
     lib.kf_graph_begin.argtypes = [P, P]
     lib.kf_graph_end.restype = I32
@@ -131,13 +135,15 @@ def make_cfg(max_cands=6, chi2_cut=30.0, n_phi=64, n_eta=16, window_margin=0.01,
                         blocks_per_cu, precision, learned_nsigma, seed_order)
 
 
-def workspace_bytes(cfg, n_events, n_seeds):
-    """kf_build_workspace_size for a configuration; the largest over the launch modes when the autotuner may
-    switch modes."""
+def workspace_bytes(cfg, n_events, n_seeds, serial=False):
+    """kf_build_workspace_size for a configuration; the largest over the grouped launch modes (tiled,
+    persistent) when the autotuner may switch between them, and over the serial-candidate mode too when
+    `serial` or when cfg asks for it (its candidate buffers take about 240 bytes per candidate slot)."""
     from . import kfmi
     lib = kfmi.load_library()
     best = 0
-    for mode in (BUILD_TILED, BUILD_PERSISTENT):
+    modes = (BUILD_TILED, BUILD_PERSISTENT) + ((BUILD_SERIAL,) if serial or cfg.mode == BUILD_SERIAL else ())
+    for mode in modes:
         c = kf_build_cfg.from_buffer_copy(cfg)
         c.mode = mode
         best = max(best, int(lib.kf_build_workspace_size(C.byref(c), int(n_events), int(n_seeds))))
@@ -296,3 +302,100 @@ def upload_problem(prob, dtype_note=None):
     hits = dict(layer_offsets=torch.from_numpy(np.asarray(prob.layer_hit_offsets, np.int64)).to(dev),
                 pos=f32(prob.hit_pos.T), cov=f32(prob.hit_cov.T))
     return seeds, hits
+
+
+class kf_build_host_args(C.Structure):
+    _fields_ = [
+        ("n_events", C.c_int64), ("n_seeds", C.c_int64), ("n_hits", C.c_int64), ("first_layer", C.c_int32),
+        ("n_chunks", C.c_int32), ("n_slots", C.c_int32),
+        ("layer_offsets", C.c_void_p), ("hit_pos", C.c_void_p), ("hit_cov", C.c_void_p),
+        ("seed_offsets", C.c_void_p), ("seed_state", C.c_void_p), ("seed_cov", C.c_void_p),
+        ("seed_charge", C.c_void_p), ("seed_hits", C.c_void_p),
+        ("n_cands", C.c_void_p), ("cand_hits", C.c_void_p), ("cand_chi2", C.c_void_p),
+        ("cand_nhits", C.c_void_p), ("cand_status", C.c_void_p), ("best_state", C.c_void_p),
+        ("best_cov", C.c_void_p), ("counters", C.c_void_p), ("mlp_packed", C.c_void_p),
+        ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
+    ]
+
+
+def host_problem(prob, pin=True):
+    """Host (page-locked when pin) tensors of a synth.BuildProblem in the kfmi.h layouts, for build_host."""
+    import numpy as np
+    import torch
+    from . import synth as S
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=dt)))
+    d = dict(layer_offsets=t(prob.layer_hit_offsets, np.int64), pos=t(prob.hit_pos.T, np.float32),
+             cov=t(prob.hit_cov.T, np.float32), seed_offsets=t(prob.seed_offsets, np.int64),
+             state=t(prob.seed_state.T, np.float32), scov=t(S.pack6(prob.seed_cov).T, np.float32),
+             charge=t(prob.seed_q, np.int8), hits=t(prob.seed_hits.T, np.int32))
+    if pin:
+        d = {k: v.pin_memory() for k, v in d.items()}
+    d["n_events"], d["n_seeds"], d["n_hits"] = prob.n_events, prob.seed_state.shape[0], prob.hit_pos.shape[0]
+    return d
+
+
+def _host_args(ctx, cfg, hp, out, n_chunks, n_slots, first_layer, counters, mlp_packed, workspace, stream):
+    import torch
+    from . import kfmi
+    for k in ("layer_offsets", "pos", "cov", "seed_offsets", "state", "scov", "charge", "hits"):
+        if hp[k].is_cuda or not hp[k].is_contiguous():
+            raise ValueError(f"{k} must be a contiguous host tensor")
+    a = kf_build_host_args()
+    a.n_events, a.n_seeds, a.n_hits = hp["n_events"], hp["n_seeds"], hp["n_hits"]
+    a.first_layer, a.n_chunks, a.n_slots = first_layer, n_chunks, n_slots
+    a.layer_offsets, a.hit_pos, a.hit_cov = _ptr(hp["layer_offsets"]), _ptr(hp["pos"]), _ptr(hp["cov"])
+    a.seed_offsets, a.seed_state, a.seed_cov = _ptr(hp["seed_offsets"]), _ptr(hp["state"]), _ptr(hp["scov"])
+    a.seed_charge, a.seed_hits = _ptr(hp["charge"]), _ptr(hp["hits"])
+    if out is not None:
+        for k, v in out.items():
+            if k.startswith("_"):
+                continue
+            if v is not None and (v.is_cuda or not v.is_contiguous()):
+                raise ValueError(f"output {k} must be a contiguous host tensor")
+        a.n_cands, a.cand_hits, a.cand_chi2 = _ptr(out["n_cands"]), _ptr(out["cand_hits"]), _ptr(out["cand_chi2"])
+        a.cand_nhits, a.cand_status = _ptr(out["cand_nhits"]), _ptr(out["cand_status"])
+        a.best_state, a.best_cov = _ptr(out.get("best_state")), _ptr(out.get("best_cov"))
+    if counters is not None and (counters.dtype != torch.int64 or counters.numel() < BUILD_COUNTERS or
+                                 not counters.is_cuda):
+        raise ValueError(f"counters must be a device tensor of {BUILD_COUNTERS} int64")
+    a.counters = _ptr(counters)
+    if cfg.window_mode == WINDOW_LEARNED:
+        if mlp_packed is None or mlp_packed.dtype != torch.uint8 or mlp_packed.numel() < 23048:
+            raise ValueError("the learned window needs the packed network (uint8, 23048 bytes)")
+        a.mlp_packed = _ptr(mlp_packed)
+    if workspace is not None:
+        a.workspace, a.workspace_bytes = _ptr(workspace), workspace.numel()
+    a.stream = kfmi._stream(stream)
+    return a
+
+
+def build_host_workspace_bytes(ctx, cfg, hp, n_chunks=4, n_slots=4, first_layer=3):
+    """kf_build_host_workspace_size for this problem (host tensors from host_problem) and chunking."""
+    from . import kfmi
+    a = _host_args(ctx, cfg, hp, None, n_chunks, n_slots, first_layer, None, None, None, None)
+    n = int(kfmi.load_library().kf_build_host_workspace_size(ctx.h, C.byref(cfg), C.byref(a)))
+    if n == 0:
+        raise ValueError("invalid problem for kf_build_host (offsets or chunking)")
+    return n
+
+
+def build_host(ctx, cfg, hp, n_chunks=4, n_slots=4, out=None, workspace=None, counters=None, mlp_packed=None,
+               first_layer=3, stream=None):
+    """kf_build_host: binning and building from host memory with overlapped copies.  hp from host_problem.
+    Returns the host output tensors (page-locked; complete once `stream` is synchronised)."""
+    import torch
+    from . import kfmi
+    S, N, L = hp["n_seeds"], cfg.max_cands, ctx.n_layers
+    if out is None:
+        e = lambda shape, dt: torch.empty(shape, dtype=dt).pin_memory()
+        out = dict(n_cands=e((S,), torch.int32), cand_hits=e((L, S, N), torch.int32),
+                   cand_chi2=e((S, N), torch.float32), cand_nhits=e((S, N), torch.int32),
+                   cand_status=e((S, N), torch.int32), best_state=e((6, S), torch.float32),
+                   best_cov=e((21, S), torch.float32))
+    if workspace is None:
+        workspace = torch.empty(build_host_workspace_bytes(ctx, cfg, hp, n_chunks, n_slots, first_layer),
+                                dtype=torch.uint8, device="cuda")
+    a = _host_args(ctx, cfg, hp, out, n_chunks, n_slots, first_layer, counters, mlp_packed, workspace, stream)
+    kfmi._check(kfmi.load_library().kf_build_host(ctx.h, C.byref(cfg), C.byref(a)))
+    out["_keep"] = (hp, workspace, counters, mlp_packed)
+    return out

@@ -159,7 +159,7 @@ def test_build_independent_of_bin_grid(ctx, n_phi, n_eta, mode):
 
 
 @pytest.mark.parametrize("N,mode,precision", [(6, 0, 1), (6, 1, 1), (1, 0, 1), (3, 0, 1), (8, 1, 1), (6, 0, 0),
-                                              (1, 1, 0)])
+                                              (1, 1, 0), (6, 2, 0), (1, 2, 0), (3, 2, 0), (8, 2, 0)])
 def test_build_parity(ctx, orc, N, mode, precision):
     det = S.detector_full()
     det32 = det.as_float32()
@@ -180,6 +180,10 @@ def test_build_deterministic_and_modes_agree(ctx):
         for k in a:
             assert np.array_equal(a[k], b[k], equal_nan=True), k
             assert np.array_equal(a[k], c[k], equal_nan=True), k
+        if precision == 0:  # the serial-candidate build (one lane per seed) gives the same outputs
+            d, _ = _gpu_build(ctx, prob, N=6, mode=2, det32=det32, precision=precision)
+            for k in a:
+                assert np.array_equal(a[k], d[k], equal_nan=True), ("serial", k)
 
 
 def test_build_edge_cases(ctx, orc):
@@ -326,3 +330,20 @@ def test_many_small_events(ctx, orc, n_events):
         assert np.array_equal(bins["perm"].cpu().numpy()[: perm.size].astype(np.int64), perm)
     ora = _oracle_build(orc, prob, det32, N=6)
     _compare(gpu, ora, label=f"{n_events} small events")
+
+
+def test_serial_build_edge_cases(ctx, orc):
+    """The serial-candidate build (one lane per seed) on the edge cases: a non-finite seed stays one stopped
+    candidate, an event without tracks, a one-track event; all other seeds as the oracle's."""
+    det = S.detector_full()
+    det32 = det.as_float32()
+    prob = S.make_build_problem([1, 0, 5, 70], det, 64)
+    prob.seed_state[2, 0] = np.nan
+    gpu, _ = _gpu_build(ctx, prob, N=6, mode=2, det32=det32, precision=0)
+    ora = _oracle_build(orc, prob, det32, N=6)
+    assert gpu["n_cands"][2] == 1 and gpu["cand_status"][2, 0] == 4
+    assert np.array_equal(gpu["cand_hits"][2, 0, :3], prob.seed_hits[2])
+    assert (gpu["cand_hits"][2, 0, 3:] == -1).all() and (gpu["cand_hits"][2, 1:] == -1).all()
+    ok = np.arange(prob.seed_state.shape[0]) != 2
+    assert np.array_equal(gpu["n_cands"][ok], ora["n_cands"][ok])
+    assert np.array_equal(gpu["cand_hits"][ok], ora["cand_hits"][ok])

@@ -222,3 +222,30 @@ def test_prebinned_build_equals_internal_binning(orc):
     outs = [orc.build(g, prob, max_cands=4, hit_cov_full=hc, seeds=ix, prebinned=(bo, perm, vm)) for ix in parts]
     for k in ("n_cands", "cand_hits", "cand_chi2", "cand_nhits", "cand_status", "best_state"):
         assert np.array_equal(np.concatenate([o[k] for o in outs]), ref[k]), k
+
+
+def test_fake_rate_order_follows_the_chi2_cut(orc):
+    """Best hit against combinatorial building on the same events (Sec. 3.2's comparison), at two chi2 cuts.
+    With a tight cut (10) the combinatorial build finds more tracks at no higher fake rate than best hit, the
+    paper's ordering.  At the loose cut of the building configuration (30) hits-first ranking lets the
+    combinatorial build take compatible hits of other tracks where best hit would also, but it keeps more of
+    them alive: its best candidates carry more foreign hits than at the tight cut, and its fake rate rises
+    above best hit's."""
+    det = S.detector_full()
+    g = orc.geometry(det)
+    prob = S.make_build_problem([9000, 7000], det, 4242)
+
+    def judged(cut, n):
+        best = orc.build(g, prob, max_cands=n, chi2_cut=cut)["cand_hits"][:, 0, :]
+        r = judge.judge_problem(prob, best)
+        valid = best >= 0
+        trk = np.where(valid, prob.hit_track[np.where(valid, best, 0)], -2)
+        r["foreign"] = float(((trk >= 0) & (trk != prob.seed_track[:, None]) & valid).sum(axis=1).mean())
+        return r
+
+    t1, t6 = judged(10.0, 1), judged(10.0, 6)
+    l1, l6 = judged(30.0, 1), judged(30.0, 6)
+    assert t6["eff"] > t1["eff"] + 0.02 and t6["fake_rate"] <= t1["fake_rate"] + 0.002
+    assert l6["eff"] > l1["eff"]
+    assert l6["foreign"] > t6["foreign"] and l6["fake_rate"] > t6["fake_rate"]
+    assert l6["fake_rate"] > l1["fake_rate"]
