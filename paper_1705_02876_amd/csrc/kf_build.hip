@@ -1354,9 +1354,11 @@ __device__ __forceinline__ void persistent_body(const BuildP& p, int64_t n_tiles
   for (;;) {
     int32_t t = 0;
     if (lane == 0) t = atomicAdd(&p.queue[c], 1);
-    t = __shfl(t, 0);
+    t = __builtin_amdgcn_readfirstlane(t);
     if (lo + t < hi) {
-      build_tile<G, T, LW>(p, lo + t, wl);
+      // the arguments are addressed through the tile number (t >> 31 is 0), so that their loads stay inside
+      // the iteration instead of being held in registers across the loop
+      build_tile<G, T, LW>((&p)[t >> 31], lo + t, wl);
       continue;
     }
     if (++k == kXcds) break;  // every chunk is exhausted
@@ -1366,17 +1368,18 @@ __device__ __forceinline__ void persistent_body(const BuildP& p, int64_t n_tiles
   }
 }
 
-// Entry kernels.  The single-precision tiled build is compiled for three waves per SIMD (at most 168
-// registers): the build is bound by the latency of its dependent LDS and memory chains, which more resident
-// waves hide.  The persistent loop keeps the arguments' scalar loads live across its iterations; under the
-// same limit it spills, so it keeps the default.
+// Entry kernels.  The single-precision tiled and persistent builds are compiled for three waves per SIMD (at
+// most 168 registers): the build is bound by the latency of its dependent LDS and memory chains, which more
+// resident waves hide.  The persistent loop addresses the arguments through its tile number, so that their
+// scalar loads are issued inside each tile rather than held in registers across the loop.
 template <int G, bool LW>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) build_tiled_kernel(BuildP p) {
   tiled_body<G, float, LW>(p);
 }
 
 template <int G, bool LW>
-__global__ void __launch_bounds__(256) build_persistent_kernel(BuildP p, int64_t n_tiles) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+build_persistent_kernel(BuildP p, int64_t n_tiles) {
   persistent_body<G, float, LW>(p, n_tiles);
 }
 

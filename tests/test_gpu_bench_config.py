@@ -92,7 +92,7 @@ def oracle_plain(orc, bench):
     return _oracle(orc, bench)
 
 
-LAUNCHES = [(0, 1, 0), (0, 2, 0), (0, 4, 0), (1, 4, 1), (1, 4, 2)]
+LAUNCHES = [(0, 1, 0), (0, 2, 0), (0, 4, 0), (1, 4, 1), (1, 4, 2), (1, 4, 3)]
 
 
 @pytest.mark.parametrize("mode,wpb,bpc", LAUNCHES)
@@ -123,7 +123,7 @@ def trained(ctx, bench):
     return tr, params
 
 
-@pytest.mark.parametrize("mode,wpb,bpc", [(0, 4, 0), (0, 1, 0), (1, 4, 2)])
+@pytest.mark.parametrize("mode,wpb,bpc", [(0, 4, 0), (0, 1, 0), (1, 4, 2), (1, 4, 3)])
 def test_bench_learned_build_matches_oracle(ctx, orc, bench, trained, mode, wpb, bpc):
     tr, params = trained
     ora = getattr(test_bench_learned_build_matches_oracle, "_ora", None)
