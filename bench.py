@@ -433,7 +433,7 @@ def learned_leg(args, ctx, det, bp, seeds, hits, bins, bout, cfg, N, fit_dev, pl
     c = cnt.cpu().numpy()
     # equal-efficiency comparison: the plain window with tighter chi2 cuts, at the plain build's launch shape
     ablation = []
-    for cut in (10.0, 15.0, 20.0):
+    for cut in () if args.no_ablation else (10.0, 15.0, 20.0):
         acfg = KB.make_cfg(max_cands=N, mode=cfg.mode, precision=cfg.precision, waves_per_block=cfg.waves_per_block,
                            blocks_per_cu=cfg.blocks_per_cu, n_phi=cfg.n_phi, n_eta=cfg.n_eta, chi2_cut=cut)
         acnt = torch.zeros(KB.BUILD_COUNTERS, dtype=torch.int64, device="cuda")
@@ -494,6 +494,8 @@ def main():
     ap.add_argument("--no-pipeline", action="store_true", help="skip the end-to-end leg from pinned host memory")
     ap.add_argument("--no-smoother", action="store_true", help="skip the smoother leg")
     ap.add_argument("--no-serial", action="store_true", help="skip the serial-candidate (one lane per seed) leg")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the plain builds with tighter chi2 cuts next to the learned window")
     ap.add_argument("--nsigma", type=float, default=2.5, help="learned window half width in network scales")
     ap.add_argument("--train-tracks", type=int, default=625_000, help="fit tracks whose residuals train the window")
     ap.add_argument("--train-steps", type=int, default=300)
