@@ -35,6 +35,7 @@ constexpr int kScanUnroll = 4;                  // work items per lane and scan 
 constexpr int kQueueCap = 64 + 64 * kScanUnroll;  // box-passing (candidate, slot) pairs awaiting their chi2
 constexpr int kQueueDefer = 256;                  // learned window: pairs outside the learned box, deferred
 constexpr int kXcds = 8;                          // accelerator dies of the device (work-queue chunks)
+constexpr int kXcdRun = 256;                      // tiled launch: consecutive blocks given to one die
 constexpr int kRangeChunk = 4;                    // slot ranges per candidate flattened together
 constexpr int kSerialMax = 8;                     // serial-candidate build: candidates per seed (max_cands <= 8)
 
@@ -1335,7 +1336,17 @@ struct MlpLds<true> {
 template <int G, typename T, bool LW>
 __device__ __forceinline__ void tiled_body(const BuildP& p) {
   const unsigned char* wl = MlpLds<LW>::stage(p.mlp);
-  const int64_t tile = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // Workgroups are dealt to the accelerator dies round robin (block b on die b % kXcds).  Blocks are renumbered so
+  // that each die takes runs of kXcdRun consecutive blocks: neighbouring tiles (neighbouring directions of one
+  // event, whose windows share hit records) then run on the same die and share its L2.  The last incomplete
+  // group of kXcds * kXcdRun blocks keeps its numbering.
+  int64_t b = blockIdx.x;
+  const int64_t grp = static_cast<int64_t>(kXcds) * kXcdRun;
+  if (b < static_cast<int64_t>(gridDim.x) / grp * grp) {
+    const int64_t r = b % grp;
+    b = b - r + (r % kXcds) * kXcdRun + r / kXcds;
+  }
+  const int64_t tile = b * (blockDim.x >> 6) + (threadIdx.x >> 6);
   build_tile<G, T, LW>(p, tile, wl);
 }
 
