@@ -404,10 +404,24 @@ __device__ __forceinline__ int phi_bin_f(float phi, int n_phi) {
   return b < 0 ? 0 : (b > n_phi - 1 ? n_phi - 1 : b);
 }
 
-__device__ __forceinline__ int eta_bin_f(float z, float R, float emax, int n_eta) {
-  const float eta = asinhf(z / R);
-  int b = static_cast<int>(floorf((eta + emax) * static_cast<float>(n_eta) / (2.f * emax)));
-  return b < 0 ? 0 : (b > n_eta - 1 ? n_eta - 1 : b);
+// asinh from the hardware base-2 logarithm and square root (each within about an ulp).  The window's eta rows
+// need it only to a few parts in a million (the rows are widened by more below), and the library's asinhf takes
+// five times the instructions, three times per candidate and layer.
+__device__ __forceinline__ float asinh_hw(float x) {
+  const float a = fabsf(x);
+  const float l2 = __builtin_amdgcn_logf(a + __builtin_amdgcn_sqrtf(fmaf(a, a, 1.f)));
+  return copysignf(l2 * 0.693147180559945309f, x);
+}
+
+// Eta row of pseudorapidity eta on a layer whose rows span [-emax, emax] in n_eta rows (escale = n_eta / 2 emax),
+// after moving eta by dir * (2e-5 + 2e-5 |eta|): the low end of a window moves down and the high end up, by more
+// than the error of asinh_hw and of the single-precision arithmetic, so that the rows cover the bins the binning
+// kernel assigns (in double precision) to every hit of the window's z interval.  Clamped in floating point, so
+// that an infinite or NaN end maps to a row.
+__device__ __forceinline__ int eta_row(float eta, float dir, float emax, float escale, int n_eta) {
+  const float e = eta + dir * (2e-5f + 2e-5f * fabsf(eta));
+  const float t = floorf((e + emax) * escale);
+  return static_cast<int>(fminf(fmaxf(t, 0.f), static_cast<float>(n_eta - 1)));
 }
 
 __device__ __forceinline__ float wrap_pi(float a) {
@@ -522,7 +536,9 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
     C.need[lane] = tighter ? 1 : 0;  // cleared by the first pair inside the learned box
   }
   const float php = atan2f(py0, px0);
-  const float emax = asinhf(p.g.z_half[l] / R);
+  const float iR = 1.f / R;
+  const float emax = asinh_hw(p.g.z_half[l] * iR);
+  const float escale = static_cast<float>(p.n_eta) / (2.f * emax);
   const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
   C.pred[0][lane] = ps[0];
   C.pred[1][lane] = ps[1];
@@ -537,17 +553,18 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
   // bins the plain window overlaps: the cyclic phi interval [ip0, ip0 + nspan) and the eta rows ie0..ie1
   int ip0 = 0, nspan = p.n_phi, ie0 = 0, ie1 = -1;
   if (live) {
-    const float sphi = wt_plain / R;
+    const float sphi = wt_plain * iR;
     if (sphi < 1.f) {
       const float dphi = asinf(sphi);
       if (dphi < 1.5707963f) {
         ip0 = phi_bin_f(wrap_pi(php - dphi), p.n_phi);
         const int ip1 = phi_bin_f(wrap_pi(php + dphi), p.n_phi);
-        nspan = ((ip1 - ip0) % p.n_phi + p.n_phi) % p.n_phi + 1;
+        const int d = ip1 - ip0;  // both in [0, n_phi): the cyclic distance without an integer division
+        nspan = (d < 0 ? d + p.n_phi : d) + 1;
       }
     }
-    ie0 = eta_bin_f(pz0 - wz_plain, R, emax, p.n_eta);
-    ie1 = eta_bin_f(pz0 + wz_plain, R, emax, p.n_eta);
+    ie0 = eta_row(asinh_hw((pz0 - wz_plain) * iR), -1.f, emax, escale, p.n_eta);
+    ie1 = eta_row(asinh_hw((pz0 + wz_plain) * iR), 1.f, emax, escale, p.n_eta);
   }
   const int first_end = (ip0 + nspan <= p.n_phi) ? ip0 + nspan : p.n_phi;
   const int wrap_end = ip0 + nspan - p.n_phi;  // > 0 if the span wraps
