@@ -51,6 +51,52 @@ __device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, d
   return ie * n_phi + ip;
 }
 
+// asinh from the hardware base-2 logarithm and square root (each within about an ulp), for the hit binning's
+// single-precision estimate and the build window's eta rows: both need it only to a few parts in a million and
+// allow for more, and the library's asinhf takes five times the instructions.
+__device__ __forceinline__ float asinh_hw(float x) {
+  const float a = fabsf(x);
+  const float l2 = __builtin_amdgcn_logf(a + __builtin_amdgcn_sqrtf(fmaf(a, a, 1.f)));
+  return copysignf(l2 * 0.693147180559945309f, x);
+}
+
+// Bin of a hit from single-precision phi and eta, falling back to hit_bin's double-precision definition only
+// where a bin edge lies within the single-precision error of the point.  The bounds taken (phi within 6 ulp of
+// atan2f plus the rounding of the sum and product, eta within 2.5e-6 (1 + |eta|) from the hardware logarithm,
+// both in bin units, with a factor of two to three to spare) exceed the single-precision error, so the bin is
+// hit_bin's in every case; a few hits in a thousand take the double-precision path.
+struct BinScale {
+  float phi_scale, eta_scale, emax, inv_r;  // n_phi / 2 pi, n_eta / 2 emax, emax = asinh(z_half / R), 1 / R
+  float dphi, deta0, deta1;                 // error bounds in bin units: dphi, and deta0 + deta1 |eta|
+};
+
+__device__ __forceinline__ BinScale bin_scale(double R, double zh, int n_phi, int n_eta) {
+  BinScale s;
+  const double emax = asinh(zh / R);
+  s.phi_scale = static_cast<float>(static_cast<double>(n_phi) / (2.0 * M_PI));
+  s.eta_scale = static_cast<float>(static_cast<double>(n_eta) / (2.0 * emax));
+  s.emax = static_cast<float>(emax);
+  s.inv_r = static_cast<float>(1.0 / R);
+  s.dphi = 1e-6f * static_cast<float>(n_phi) + 1e-6f;
+  s.deta0 = 5e-6f * s.eta_scale + 1e-6f * static_cast<float>(n_eta) + 1e-6f;
+  s.deta1 = 5e-6f * s.eta_scale;
+  return s;
+}
+
+__device__ __forceinline__ int hit_bin_fast(float x, float y, float z, const BinScale& s, double R, double zh,
+                                            int n_phi, int n_eta) {
+  const float tp = (atan2f(y, x) + 3.14159265358979f) * s.phi_scale;
+  const float eta = asinh_hw(z * s.inv_r);
+  const float te = (eta + s.emax) * s.eta_scale;
+  const float de = s.deta0 + s.deta1 * fabsf(eta);
+  const float pm = static_cast<float>(n_phi - 1), em = static_cast<float>(n_eta - 1);
+  const float p0 = fminf(fmaxf(floorf(tp - s.dphi), 0.f), pm), p1 = fminf(fmaxf(floorf(tp + s.dphi), 0.f), pm);
+  const float e0 = fminf(fmaxf(floorf(te - de), 0.f), em), e1 = fminf(fmaxf(floorf(te + de), 0.f), em);
+  if (fabsf(tp) < 1e30f && fabsf(te) < 1e30f && p0 == p1 && e0 == e1)
+    return static_cast<int>(e0) * n_phi + static_cast<int>(p0);
+  return hit_bin(x, y, z, R, zh, n_phi, n_eta);
+}
+
 // Launch order of the binning blocks: (event, layer) pairs by decreasing hit count (ties by index), so that
 // the largest pairs start first and the small ones fill in behind them (event sizes span a factor of 50; in
 // index order a large pair starting late holds the whole launch).  One block; the rank of each pair is counted
@@ -107,9 +153,10 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
   const int64_t b = (a + per < hi) ? a + per : hi;
   const double R = static_cast<double>(g.r[l]);
   const double zh = static_cast<double>(g.z_half[l]);
+  const BinScale bs = bin_scale(R, zh, n_phi, n_eta);
   float my_vxy = 0.f, my_vz = 0.f;
   for (int64_t h = a + lane; h < b; h += 64) {
-    const int bin = hit_bin(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h], R, zh, n_phi, n_eta);
+    const int bin = hit_bin_fast(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h], bs, R, zh, n_phi, n_eta);
     bins[h] = bin;
     atomicAdd(&cnt(wave, bin), 1);
     const float vxx = hit_cov[h], vyx = hit_cov[ldh + h], vyy = hit_cov[2 * ldh + h], vzz = hit_cov[5 * ldh + h];
@@ -215,7 +262,11 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
 // Binning for fine grids (more bins than the per-wave histograms hold): one
 // LDS histogram per (event, layer) with atomics, a block scan, an unordered
 // scatter of hit indices, then each bin's segment sorted by hit index (bins are
-// small), so the result is the same stable order as bin_kernel's.
+// small), so the result is the same stable order as bin_kernel's.  A block of
+// 1024 threads owns one (event, layer) pair; the memory passes take several
+// hits per thread with their loads issued together, since each is a chain of
+// dependent accesses and one compute unit holds one block.
+constexpr int kFineUnroll = 4;  // hits per thread and iteration of the memory passes
 __global__ void __launch_bounds__(kBinThreads) bin_fine_kernel(int32_t L, const int64_t* __restrict__ layer_offsets,
                                                                const float* __restrict__ hit_pos,
                                                                const float* __restrict__ hit_cov, int64_t ldh,
@@ -225,9 +276,11 @@ __global__ void __launch_bounds__(kBinThreads) bin_fine_kernel(int32_t L, const 
                                                                int32_t* __restrict__ perm, float* __restrict__ binned,
                                                                float* __restrict__ layer_vmax,
                                                                const int32_t* __restrict__ el_order) {
-  extern __shared__ int32_t cnt_fine[];  // [nb] counts, then scatter cursors
+  extern __shared__ int32_t cnt_fine[];  // [nb] counts, then scatter cursors, which end as the bins' ends
   __shared__ int32_t wsum[kBinWaves];
   __shared__ uint32_t vmax_bits[2];
+  constexpr int U = kFineUnroll;
+  constexpr int64_t kStep = static_cast<int64_t>(kBinThreads) * U;
   const int el = el_order ? el_order[blockIdx.x] : static_cast<int>(blockIdx.x);
   const int l = el % L;
   const int nb = n_phi * n_eta;
@@ -240,9 +293,10 @@ __global__ void __launch_bounds__(kBinThreads) bin_fine_kernel(int32_t L, const 
   __syncthreads();
   const double R = static_cast<double>(g.r[l]);
   const double zh = static_cast<double>(g.z_half[l]);
+  const BinScale bs = bin_scale(R, zh, n_phi, n_eta);
   float my_vxy = 0.f, my_vz = 0.f;
   for (int64_t h = lo + tid; h < hi; h += kBinThreads) {
-    const int bin = hit_bin(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h], R, zh, n_phi, n_eta);
+    const int bin = hit_bin_fast(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h], bs, R, zh, n_phi, n_eta);
     bins[h] = bin;
     atomicAdd(&cnt_fine[bin], 1);
     const float vxx = hit_cov[h], vyx = hit_cov[ldh + h], vyy = hit_cov[2 * ldh + h], vzz = hit_cov[5 * ldh + h];
@@ -293,38 +347,96 @@ __global__ void __launch_bounds__(kBinThreads) bin_fine_kernel(int32_t L, const 
     layer_vmax[2 * el + 1] = __uint_as_float(vmax_bits[1]);
   }
   __syncthreads();
-  // unordered scatter of hit indices
-  for (int64_t h = lo + tid; h < hi; h += kBinThreads) {
-    const int at = atomicAdd(&cnt_fine[bins[h]], 1);
-    perm[lo + at] = static_cast<int32_t>(h);
+  // unordered scatter of hit indices; afterwards cnt_fine[b] is the end of bin b (the start of bin b + 1)
+  for (int64_t h0 = lo + tid; h0 < hi; h0 += kStep) {
+    int32_t b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t h = h0 + u * kBinThreads;
+      b[u] = h < hi ? bins[h] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t h = h0 + u * kBinThreads;
+      if (h < hi) perm[lo + atomicAdd(&cnt_fine[b[u]], 1)] = static_cast<int32_t>(h);
+    }
   }
   __syncthreads();
-  // each bin's segment in hit-index order (insertion sort; a bin holds a few hits)
+  // each bin's segment in hit-index order, its bounds from LDS: up to eight hits are loaded at once and sorted
+  // in registers by a sorting network (Batcher's odd-even merge sort of eight), longer segments by insertion
   for (int bin = tid; bin < nb; bin += kBinThreads) {
-    const int64_t s0 = bo[bin], s1 = (bin + 1 < nb) ? static_cast<int64_t>(bo[bin + 1]) : hi;
-    for (int64_t i = s0 + 1; i < s1; ++i) {
-      const int32_t v = perm[i];
-      int64_t j = i - 1;
-      while (j >= s0 && perm[j] > v) {
-        perm[j + 1] = perm[j];
-        --j;
+    const int64_t s0 = lo + (bin > 0 ? cnt_fine[bin - 1] : 0), s1 = lo + cnt_fine[bin];
+    const int64_t len = s1 - s0;
+    if (len < 2) continue;
+    if (len <= 8) {
+      int32_t v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = k < len ? perm[s0 + k] : INT32_MAX;
+      constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
+                                   {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+      for (int c = 0; c < 19; ++c) {
+        const int32_t x = v[kNet[c][0]], y = v[kNet[c][1]];
+        v[kNet[c][0]] = min(x, y);
+        v[kNet[c][1]] = max(x, y);
       }
-      perm[j + 1] = v;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < len) perm[s0 + k] = v[k];
+    } else {
+      for (int64_t i = s0 + 1; i < s1; ++i) {
+        const int32_t v = perm[i];
+        int64_t j = i - 1;
+        while (j >= s0 && perm[j] > v) {
+          perm[j + 1] = perm[j];
+          --j;
+        }
+        perm[j + 1] = v;
+      }
     }
   }
   __syncthreads();
   // Records: the inverse permutation (into the bin-number array, no longer needed) lets the hits be read in index
-  // order, coalesced, and each record be written to its slot.  Gathering the hits in slot order instead reads a
-  // scattered word per access from hit arrays that, over all blocks of a die, do not fit in its L2.
-  for (int64_t slot = lo + tid; slot < hi; slot += kBinThreads) bins[perm[slot]] = static_cast<int32_t>(slot - lo);
+  // order, coalesced, and each record be written to its slot.  Gathering the hits in slot order instead reads
+  // scattered words from hit arrays that, over all blocks of a die, do not fit in its L2 (measured three times
+  // slower).
+  for (int64_t s0 = lo + tid; s0 < hi; s0 += kStep) {
+    int32_t hh[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t slot = s0 + u * kBinThreads;
+      hh[u] = slot < hi ? perm[slot] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t slot = s0 + u * kBinThreads;
+      if (slot < hi) bins[hh[u]] = static_cast<int32_t>(slot - lo);
+    }
+  }
   __syncthreads();
-  for (int64_t h = lo + tid; h < hi; h += kBinThreads) {
-    const int64_t slot = lo + bins[h];
-    float4* rec = reinterpret_cast<float4*>(binned + slot * KF_BINNED_FLOATS);
-    rec[0] = make_float4(hit_pos[h], hit_pos[ldh + h], hit_pos[2 * ldh + h],
-                         __int_as_float(static_cast<int32_t>(h - lo)));
-    rec[1] = make_float4(hit_cov[h], hit_cov[ldh + h], hit_cov[2 * ldh + h], hit_cov[3 * ldh + h]);
-    rec[2] = make_float4(hit_cov[4 * ldh + h], hit_cov[5 * ldh + h], 0.f, 0.f);
+  for (int64_t h0 = lo + tid; h0 < hi; h0 += kStep) {
+    int32_t sl[U];
+    float4 r0[U], r1[U], r2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t h = h0 + u * kBinThreads;
+      const int64_t hc = h < hi ? h : h0;
+      sl[u] = bins[hc];
+      r0[u] = make_float4(hit_pos[hc], hit_pos[ldh + hc], hit_pos[2 * ldh + hc],
+                          __int_as_float(static_cast<int32_t>(hc - lo)));
+      r1[u] = make_float4(hit_cov[hc], hit_cov[ldh + hc], hit_cov[2 * ldh + hc], hit_cov[3 * ldh + hc]);
+      r2[u] = make_float4(hit_cov[4 * ldh + hc], hit_cov[5 * ldh + hc], 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t h = h0 + u * kBinThreads;
+      if (h < hi) {
+        float4* rec = reinterpret_cast<float4*>(binned + (lo + sl[u]) * KF_BINNED_FLOATS);
+        rec[0] = r0[u];
+        rec[1] = r1[u];
+        rec[2] = r2[u];
+      }
+    }
   }
 }
 
@@ -404,15 +516,6 @@ __device__ __forceinline__ int phi_bin_f(float phi, int n_phi) {
   return b < 0 ? 0 : (b > n_phi - 1 ? n_phi - 1 : b);
 }
 
-// asinh from the hardware base-2 logarithm and square root (each within about an ulp).  The window's eta rows
-// need it only to a few parts in a million (the rows are widened by more below), and the library's asinhf takes
-// five times the instructions, three times per candidate and layer.
-__device__ __forceinline__ float asinh_hw(float x) {
-  const float a = fabsf(x);
-  const float l2 = __builtin_amdgcn_logf(a + __builtin_amdgcn_sqrtf(fmaf(a, a, 1.f)));
-  return copysignf(l2 * 0.693147180559945309f, x);
-}
-
 // Eta row of pseudorapidity eta on a layer whose rows span [-emax, emax] in n_eta rows (escale = n_eta / 2 emax),
 // after moving eta by dir * (2e-5 + 2e-5 |eta|): the low end of a window moves down and the high end up, by more
 // than the error of asinh_hw and of the single-precision arithmetic, so that the rows cover the bins the binning
@@ -479,15 +582,117 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+// A candidate's best children, in rank order: accumulated chi2, hit index within the (event, layer) (bit 30 set:
+// outside the learned box, ranked after every hit inside it) and slot.  insert() keeps them sorted by (flag,
+// chi2, index); positions past the N a build keeps hold children that are never used.
+template <typename T, int Q>
+struct ChildList {
+  T key[Q];
+  int32_t idx[Q], slot[Q];
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      key[t] = T(INFINITY);
+      idx[t] = 0x7FFFFFFF;
+      slot[t] = 0;
+    }
+  }
+  __device__ __forceinline__ void insert(T nk, int32_t ni, int32_t nj, bool flags) {
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      bool sw;
+      if (flags) {
+        const int fn = ni >> 30, ft = idx[t] >> 30;
+        sw = fn < ft || (fn == ft && (nk < key[t] || (nk == key[t] && ni < idx[t])));
+      } else {
+        sw = nk < key[t] || (nk == key[t] && ni < idx[t]);
+      }
+      const T tk = key[t];
+      const int32_t ti = idx[t], tj = slot[t];
+      key[t] = sw ? nk : tk;
+      idx[t] = sw ? ni : ti;
+      slot[t] = sw ? nj : tj;
+      nk = sw ? tk : nk;
+      ni = sw ? ti : ni;
+      nj = sw ? tj : nj;
+    }
+  }
+  __device__ __forceinline__ T chi2_at(int t) const { return key[t]; }
+  __device__ __forceinline__ int32_t idx_at(int t) const { return idx[t]; }
+  __device__ __forceinline__ int32_t slot_at(int t) const { return slot[t]; }
+  __device__ __forceinline__ void pop() {
+#pragma unroll
+    for (int t = 0; t + 1 < Q; ++t) {
+      key[t] = key[t + 1];
+      idx[t] = idx[t + 1];
+      slot[t] = slot[t + 1];
+    }
+    key[Q - 1] = T(INFINITY);
+  }
+  __device__ __forceinline__ void strip_flags() {
+#pragma unroll
+    for (int t = 0; t < Q; ++t) idx[t] &= 0x3FFFFFFF;
+  }
+};
+
+// Single precision: the flag, the chi2's bits (non-negative floats order as their bits) and the index form one
+// 64-bit key that orders as the comparison above, so an insertion compares once per position, and every
+// position's new value depends only on its own comparison and its left neighbour's (no chain along the list).
+template <int Q>
+struct ChildList<float, Q> {
+  uint64_t key[Q];  // flag << 63 | chi2 bits << 32 | index without its flag; empty: all ones
+  int32_t slot[Q];
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      key[t] = ~0ull;
+      slot[t] = 0;
+    }
+  }
+  __device__ __forceinline__ void insert(float nk, int32_t ni, int32_t nj, bool) {
+    const uint64_t nkey = (static_cast<uint64_t>((static_cast<uint32_t>(ni) >> 30) & 1u) << 63) |
+                          (static_cast<uint64_t>(__float_as_uint(nk)) << 32) |
+                          static_cast<uint32_t>(ni & 0x3FFFFFFF);
+    bool lt[Q];
+#pragma unroll
+    for (int t = 0; t < Q; ++t) lt[t] = nkey < key[t];
+#pragma unroll
+    for (int t = Q - 1; t >= 0; --t) {
+      const bool shift = t > 0 && lt[t - 1];
+      key[t] = shift ? key[t - 1] : (lt[t] ? nkey : key[t]);
+      slot[t] = shift ? slot[t - 1] : (lt[t] ? nj : slot[t]);
+    }
+  }
+  __device__ __forceinline__ float chi2_at(int t) const {
+    return __uint_as_float(static_cast<uint32_t>(key[t] >> 32) & 0x7FFFFFFFu);
+  }
+  __device__ __forceinline__ int32_t idx_at(int t) const {
+    return static_cast<int32_t>(static_cast<uint32_t>(key[t]) | (static_cast<uint32_t>(key[t] >> 63) << 30));
+  }
+  __device__ __forceinline__ int32_t slot_at(int t) const { return slot[t]; }
+  __device__ __forceinline__ void pop() {
+#pragma unroll
+    for (int t = 0; t + 1 < Q; ++t) {
+      key[t] = key[t + 1];
+      slot[t] = slot[t + 1];
+    }
+    key[Q - 1] = ~0ull;
+  }
+  __device__ __forceinline__ void strip_flags() {
+#pragma unroll
+    for (int t = 0; t < Q; ++t) key[t] &= ~(1ull << 63);
+  }
+};
+
 // Scans the plain window of this lane's candidate (the wave's 64 candidates together) and leaves in
-// lkey / lidx / lslot the candidate's best children by (chi2, hit index): their accumulated chi2, hit index
+// kids the candidate's best children by (chi2, hit index): their accumulated chi2, hit index
 // within the (event, layer) and slot, cnt of them (at most N); with the learned window, the definition of the
 // learned search window with its fallback (see below).  Wave-uniform work counters are accumulated.
 template <int Q, typename T, bool LW>
 __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, const unsigned char* mlp_lds, int l,
                                             int64_t el, bool live, const T (&ps)[6], const T (&pc)[21], float qf,
                                             T chi2, int N, int lane, uint64_t lanes_below, const float4* recs,
-                                            T (&lkey)[Q], int32_t (&lidx)[Q], int32_t (&lslot)[Q], int& cnt,
+                                            ChildList<T, Q>& kids, int& cnt,
                                             int& cnt_in, uint32_t& n_box, uint32_t& n_chi2, uint32_t& n_comp,
                                             uint32_t& n_fb) {
   // Window geometry of this lane's candidate (dead lanes only work for others).
@@ -586,6 +791,12 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
     }
   };
   int qn = 0;  // pairs awaiting their chi2, carried across the ranges
+  int qh = 0;  // ring position of the oldest of them: the queue is a ring of kQueueCap entries (never more queued)
+  // ring position of the pair k places after the oldest (k < kQueueCap)
+  auto qpos = [&](int k) {
+    const int r = qh + k;
+    return r >= kQueueCap ? r - kQueueCap : r;
+  };
   int qb = 0;  // learned window: pairs inside the plain box but outside the learned one, waiting
   // Evaluates the queue 64 pairs at a time (all of it when final) and inserts the compatible hits into the
   // owners' lists.  A queued owner with bit 6 set marks a pair outside the learned box: its hit is flagged
@@ -598,8 +809,9 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
       T c2 = T(0);
       int32_t hidx = 0, jq = 0, oq = 0;
       if (lane < nb) {
-        jq = C.q_slot[lane];
-        const int qo = C.q_own[lane];
+        const int qi = qpos(lane);
+        jq = C.q_slot[qi];
+        const int qo = C.q_own[qi];
         oq = qo & 63;
         const float4 h = recs[static_cast<int64_t>(jq) * 3];
         const float4 c0 = recs[static_cast<int64_t>(jq) * 3 + 1];
@@ -649,53 +861,19 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
         C.r_slot[rp] = jq;
         C.r_c2[rp] = c2;
       }
-      // move the unevaluated rest of the queue to its front
-      const int rest = qn - nb;
-      int keep_s[kScanUnroll + 1], keep_o[kScanUnroll + 1];
-#pragma unroll
-      for (int u = 0; u <= kScanUnroll; ++u) {
-        const int from = nb + 64 * u + lane;
-        keep_s[u] = from < qn ? C.q_slot[from] : 0;
-        keep_o[u] = from < qn ? C.q_own[from] : 0;
-      }
-      wave_lds_sync();
-#pragma unroll
-      for (int u = 0; u <= kScanUnroll; ++u) {
-        const int to = 64 * u + lane;
-        if (to < rest) {
-          C.q_slot[to] = keep_s[u];
-          C.q_own[to] = static_cast<uint8_t>(keep_o[u]);
-        }
-      }
-      qn = rest;
+      // the batch leaves the ring
+      qh = qpos(nb);
+      qn -= nb;
       wave_lds_sync();
       const int rounds = wave_max_i(count);
       for (int k = 0; k < rounds; ++k) {
         if (k < count) {
           const int e = first + k;
           const T cc = C.r_c2[e];
-          T nk = chi2 + (cc > T(0) ? cc : T(0));
-          int32_t ni = C.r_idx[e];
-          int32_t nj = C.r_slot[e];
+          const T nk = chi2 + (cc > T(0) ? cc : T(0));
+          const int32_t ni = C.r_idx[e];
           if (LW && (ni >> 30) == 0) cnt_in = cnt_in + 1 < N ? cnt_in + 1 : N;
-#pragma unroll
-          for (int t = 0; t < Q; ++t) {
-            bool sw;
-            if (LW) {
-              const int fn = ni >> 30, ft = lidx[t] >> 30;
-              sw = (t < N) && (fn < ft || (fn == ft && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]))));
-            } else {
-              sw = (t < N) && (nk < lkey[t] || (nk == lkey[t] && ni < lidx[t]));
-            }
-            const T tk = lkey[t];
-            const int32_t ti = lidx[t], tj = lslot[t];
-            lkey[t] = sw ? nk : tk;
-            lidx[t] = sw ? ni : ti;
-            lslot[t] = sw ? nj : tj;
-            nk = sw ? tk : nk;
-            ni = sw ? ti : ni;
-            nj = sw ? tj : nj;
-          }
+          kids.insert(nk, ni, C.r_slot[e], LW);
           cnt = cnt + 1 < N ? cnt + 1 : N;
         }
       }
@@ -716,7 +894,7 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
       }
       const uint64_t mt = __ballot(take);
       if (take) {
-        const int pos = qn + __popcll(mt & lanes_below);
+        const int pos = qpos(qn + __popcll(mt & lanes_below));
         C.q_slot[pos] = jb;
         C.q_own[pos] = static_cast<uint8_t>(ob | 64);
       }
@@ -807,7 +985,7 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
         }
         const uint64_t m = __ballot(to_q);
         if (to_q) {
-          const int pos = qn + __popcll(m & lanes_below);
+          const int pos = qpos(qn + __popcll(m & lanes_below));
           C.q_slot[pos] = js[u];
           C.q_own[pos] = static_cast<uint8_t>(own[u] | flag);
         }
@@ -836,8 +1014,7 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
     }
     // a candidate with a compatible hit inside its learned box keeps only those (they rank first)
     if (cnt_in > 0) cnt = cnt_in;
-#pragma unroll
-    for (int t = 0; t < Q; ++t) lidx[t] &= 0x3FFFFFFF;
+    kids.strip_flags();
   }
 }
 
@@ -916,18 +1093,12 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       }
     }
     // ---- scan the window's bins, keep the best N children of this candidate
-    T lkey[G];
-    int32_t lidx[G], lslot[G];
-#pragma unroll
-    for (int t = 0; t < G; ++t) {
-      lkey[t] = T(INFINITY);
-      lidx[t] = 0x7FFFFFFF;
-      lslot[t] = 0;
-    }
+    ChildList<T, G> kids;
+    kids.clear();
     int cnt = 0;     // children in the list (at most N)
     int cnt_in = 0;  // learned window: those inside the learned box (at most N)
     scan_window<G, T, LW>(p, C, mlp_lds, l, el, active && pstat == 0, ps, pc, qf, chi2, N, lane, lanes_below, recs,
-                          lkey, lidx, lslot, cnt, cnt_in, n_box, n_chi2, n_comp, n_fb);
+                          kids, cnt, cnt_in, n_box, n_chi2, n_comp, n_fb);
     // ---- merge the seed's lists: N rounds of a G-lane minimum of the rank key
     bool hole_left = active;
     uint64_t mine = ~0ull;  // the child that becomes this slot's candidate
@@ -938,14 +1109,14 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       uint64_t k = ~0ull;
       const bool has_hit = active && pstat == 0 && cnt > 0;
       if (has_hit)
-        k = make_key(nhits + 1, float(lkey[0]), slot, static_cast<uint32_t>(lidx[0]));
+        k = make_key(nhits + 1, float(kids.chi2_at(0)), slot, static_cast<uint32_t>(kids.idx_at(0)));
       else if (hole_left)
         k = make_key(nhits, float(chi2), slot, kHole);
       const uint64_t kmin = group_min<G>(k);
       if (__ballot(kmin != ~0ull) == 0) break;  // no seed of the wave has a child left
       const int winner = gbase + key_parent(kmin);
-      const int32_t wslot = __shfl(has_hit ? lslot[0] : -1, winner);
-      const T wchi2 = __shfl(has_hit ? lkey[0] : chi2, winner);
+      const int32_t wslot = __shfl(has_hit ? kids.slot_at(0) : -1, winner);
+      const T wchi2 = __shfl(has_hit ? kids.chi2_at(0) : chi2, winner);
       if (kmin != ~0ull) {
         new_nc = r + 1;
         if (slot == r) {
@@ -955,13 +1126,7 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
         }
         if (k == kmin) {
           if (has_hit) {
-#pragma unroll
-            for (int t = 0; t + 1 < G; ++t) {
-              lkey[t] = lkey[t + 1];
-              lidx[t] = lidx[t + 1];
-              lslot[t] = lslot[t + 1];
-            }
-            lkey[G - 1] = T(INFINITY);
+            kids.pop();
             cnt--;
           } else {
             hole_left = false;
@@ -1188,18 +1353,11 @@ __device__ void build_serial_tile(const BuildP& p, int64_t tile) {
         for (int k = 0; k < 21; ++k) at(cur, c, 6 + k) = pc[k];
         at(cur, c, 29) = __int_as_float(pstat);
       }
-      T lkey[kSerialMax];
-      int32_t lidx[kSerialMax], lslot[kSerialMax];
-#pragma unroll
-      for (int t = 0; t < kSerialMax; ++t) {
-        lkey[t] = T(INFINITY);
-        lidx[t] = 0x7FFFFFFF;
-        lslot[t] = 0;
-      }
+      ChildList<T, kSerialMax> kids;
+      kids.clear();
       int cnt = 0, cnt_in = 0;
       scan_window<kSerialMax, T, false>(p, C, nullptr, l, el, active && pstat == 0, ps, pc, qf, chi2, N, lane,
-                                        lanes_below, recs, lkey, lidx, lslot, cnt, cnt_in, n_box, n_chi2, n_comp,
-                                        n_fb);
+                                        lanes_below, recs, kids, cnt, cnt_in, n_box, n_chi2, n_comp, n_fb);
       // the candidate's children into the seed's list: its compatible hits (if it was propagated), else or
       // besides them its hole child
       if (active) {
@@ -1210,9 +1368,9 @@ __device__ void build_serial_tile(const BuildP& p, int64_t tile) {
           float nc2;
           if (t < kSerialMax) {
             if (!(pstat == 0 && t < cnt)) continue;
-            nk = make_key(nhits + 1, float(lkey[t]), c, static_cast<uint32_t>(lidx[t]));
-            nj = lslot[t];
-            nc2 = float(lkey[t]);
+            nk = make_key(nhits + 1, float(kids.chi2_at(t)), c, static_cast<uint32_t>(kids.idx_at(t)));
+            nj = kids.slot_at(t);
+            nc2 = float(kids.chi2_at(t));
           } else {
             nk = make_key(nhits, float(chi2), c, kHole);
             nj = -1;

@@ -245,6 +245,20 @@ KF_DEV int32_t propagate(T s[6], T c[21], T a, T R, T zh) {
   return 0;
 }
 
+// Propagate + transport in place for callers that keep the state themselves: the same results as propagate on
+// success, unspecified s and c on failure (no copy of the covariance is made).
+template <typename T>
+KF_DEV int32_t propagate_inplace(T s[6], T c[21], T a, T R, T zh) {
+  if (!finite6_21(s, c)) return ST_NONFINITE;
+  Prop<T> p;
+  const int32_t st = helix_to_r(s, a, R, zh, p);
+  if (st) return st;
+  transport(c, p);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[k] = p.s[k];
+  return finite6_21(s, c) ? 0 : ST_NONFINITE;
+}
+
 // Thin scatterer (multiple scattering, Highland width, and mean energy loss)
 // for a track sitting on a layer of normal thickness xx0 radiation lengths.
 // f_out (nullable) receives the momentum ratio p'/p of the energy loss.

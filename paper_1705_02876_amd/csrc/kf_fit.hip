@@ -169,16 +169,21 @@ __device__ __forceinline__ void fit_body(I n, I ld, const float* state_in, const
   // layer and step that failed: 0 its crossing or its update (one step: the state before the layer is kept),
   // 1 its material (the state after the update is kept)
   int fail_l = 0, fail_step = 0;
+  // A failing lane stops stepping (ok turns false) but stays in the loop, so that the state registers are the
+  // loop's own on every path (an exit from the loop would copy the covariance into other registers at each layer).
+  bool ok = true;
   for (int l = 0; l <= last; ++l) {
+    if (!ok) continue;
     const int32_t h_cur = h_nxt;
     float m[3], v[6];
     load_hit(hit_pos, hit_cov, ldh, h_cur >= 0 ? h_cur : 0, m, v);
     h_nxt = (l + 1 <= last) ? *elem(hit_idx + (l + 1) * static_cast<int64_t>(ld_idx), i) : -1;
-    st = propagate(s, c, a, T(g.r[l]), T(0));
+    st = propagate_inplace(s, c, a, T(g.r[l]), T(0));  // a failure is replayed below
     if (st) {
       fail_l = l;
       fail_step = 0;
-      break;
+      ok = false;
+      continue;
     }
     if (h_cur >= 0) {
       T dc2;
@@ -187,7 +192,8 @@ __device__ __forceinline__ void fit_body(I n, I ld, const float* state_in, const
       if (st) {
         fail_l = l;
         fail_step = 0;
-        break;
+        ok = false;
+        continue;
       }
       chi2 += dc2;
       nh += 1;
@@ -198,7 +204,7 @@ __device__ __forceinline__ void fit_body(I n, I ld, const float* state_in, const
       if (st) {
         fail_l = l;
         fail_step = 1;
-        break;
+        ok = false;
       }
     }
   }
@@ -334,7 +340,7 @@ __device__ __forceinline__ void smooth_fwd_body(I n, I ld, const float* state_in
       float m[3], v[6];
       load_hit(hit_pos, hit_cov, ldh, h_cur >= 0 ? h_cur : 0, m, v);
       h_nxt = (l + 1 <= last) ? *elem(hit_idx + (l + 1) * static_cast<int64_t>(ld_idx), i) : -1;
-      st = propagate(s, c, a, T(g.r[l]), T(0));
+      st = propagate_inplace(s, c, a, T(g.r[l]), T(0));  // a failure ends the track (its rows are NaN)
       if (!st && h_cur >= 0) {
         T dc2;
         st = update_on_layer<T, double>(s, c, m, v, dc2);
