@@ -39,6 +39,22 @@ constexpr int kXcdRun = 256;                      // tiled launch: consecutive b
 constexpr int kRangeChunk = 4;                    // slot ranges per candidate flattened together
 constexpr int kSerialMax = 8;                     // serial-candidate build: candidates per seed (max_cands <= 8)
 
+// Inclusive prefix sum (Max false) or maximum (Max true) over the wave's 64 lanes from DPP lane moves, with no
+// LDS traffic: shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the rows joined by broadcasting lanes 15
+// and 31 to the rows after them.  Lanes shifted in from outside a row read 0, the identity of both (maxima are
+// taken of non-negative values).  All lanes of the wave take part.
+template <bool Max>
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  auto op = [](int a, int b) { return Max ? max(a, b) : a + b; };
+  x = op(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true));   // row_shr:1
+  x = op(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true));   // row_shr:2
+  x = op(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true));   // row_shr:4
+  x = op(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true));   // row_shr:8
+  x = op(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false));  // row_bcast:15 into rows 1 and 3
+  x = op(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false));  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 __device__ __forceinline__ int hit_bin(float xf, float yf, float zf, double R, double zh, int n_phi, int n_eta) {
 #pragma clang fp contract(off)
   const double phi = atan2(static_cast<double>(yf), static_cast<double>(xf));
@@ -187,14 +203,9 @@ __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64
   for (int base = b0; base < b1; base += 64) {
     const int bin = base + lane;
     int v = (bin < b1) ? tot[bin] : 0;
-    int x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(x, off);
-      if (lane >= off) x += y;
-    }
+    const int x = wave_incl_scan<false>(v);
     if (bin < b1) tot[bin] = wrun + x - v;  // exclusive within this wave's block
-    wrun += __shfl(x, 63);
+    wrun += __builtin_amdgcn_readlane(x, 63);
   }
   if (lane == 0) wsum[wave] = wrun;
   __syncthreads();
@@ -315,14 +326,9 @@ __global__ void __launch_bounds__(kBinThreads) bin_fine_kernel(int32_t L, const 
   for (int base = b0; base < b1; base += 64) {
     const int bin = base + lane;
     const int v = (bin < b1) ? cnt_fine[bin] : 0;
-    int x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(x, off);
-      if (lane >= off) x += y;
-    }
+    const int x = wave_incl_scan<false>(v);
     if (bin < b1) cnt_fine[bin] = wrun + x - v;
-    wrun += __shfl(x, 63);
+    wrun += __builtin_amdgcn_readlane(x, 63);
   }
   if (lane == 0) wsum[wave] = wrun;
   __syncthreads();
@@ -576,11 +582,11 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-  return v;
-}
+// the value of the lane below (0 in lane 0), by a DPP shift of the whole wave
+__device__ __forceinline__ int wave_shift_up1(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true); }
+
+// maximum of a non-negative value over the wave, uniform
+__device__ __forceinline__ int wave_max_i(int v) { return __builtin_amdgcn_readlane(wave_incl_scan<true>(v), 63); }
 
 // A candidate's best children, in rank order: accumulated chi2, hit index within the (event, layer) (bit 30 set:
 // outside the learned box, ranked after every hit inside it) and slot.  insert() keeps them sorted by (flag,
@@ -846,12 +852,7 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
       const int rank = comp ? atomicAdd(&C.cnt[oq], 1) : 0;
       wave_lds_sync();
       const int count = C.cnt[lane];
-      int cinc = count;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(cinc, o);
-        if (lane >= o) cinc += y;
-      }
+      const int cinc = wave_incl_scan<false>(count);
       const int first = cinc - count;
       C.rstart[lane] = first;
       wave_lds_sync();
@@ -916,27 +917,46 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
       C.rst[j][lane] = ra[j];
       mine += rn[j];
     }
-    int incl = mine;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(incl, o);
-      if (lane >= o) incl += y;
-    }
-    const int total = __shfl(incl, 63);
+    const int incl = wave_incl_scan<false>(mine);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
     C.off[lane] = incl - mine;
     wave_lds_sync();
+    const int my_off = incl - mine;
+    int carry = 0;  // owner lane + 1 of the item before the current block of items (0: none)
     for (int base = 0; base < total; base += 64 * kScanUnroll) {
       n_box += min(total - base, 64 * kScanUnroll);
+      // Owners of the block's 64 kScanUnroll items: each lane whose items start inside the block marks its first
+      // item with its lane + 1, and an item's owner is the largest mark at or before it, or the carry (lanes with
+      // items are in item order).  The marks sit in the batch result table, which is idle until the flush.
+      static_assert(64 * kScanUnroll == 256, "one byte of the 256-byte owner table per item");
+      uint32_t* const own4 = reinterpret_cast<uint32_t*>(C.r_idx);
+      const uint8_t* const own1 = reinterpret_cast<const uint8_t*>(C.r_idx);
+      wave_lds_sync();
+      own4[lane] = 0u;
+      wave_lds_sync();
+      if (mine > 0 && my_off >= base && my_off < base + 256)
+        reinterpret_cast<uint8_t*>(C.r_idx)[my_off - base] = static_cast<uint8_t>(lane + 1);
+      wave_lds_sync();
+      const uint32_t h4 = own4[lane];  // items base + 4 lane .. base + 4 lane + 3
+      const int m0 = static_cast<int>(h4 & 0xFFu), m1 = max(m0, static_cast<int>((h4 >> 8) & 0xFFu));
+      const int m2 = max(m1, static_cast<int>((h4 >> 16) & 0xFFu)), m3 = max(m2, static_cast<int>(h4 >> 24));
+      const int sc = wave_incl_scan<true>(m3);  // inclusive maximum over the lanes
+      const int before = max(wave_shift_up1(sc), carry);
+      const uint32_t ow = static_cast<uint32_t>(max(before, m0)) | (static_cast<uint32_t>(max(before, m1)) << 8) |
+                          (static_cast<uint32_t>(max(before, m2)) << 16) |
+                          (static_cast<uint32_t>(max(before, m3)) << 24);
+      carry = max(carry, __builtin_amdgcn_readlane(sc, 63));
+      wave_lds_sync();
+      own4[lane] = ow;  // the owners in item order
+      wave_lds_sync();
       int own[kScanUnroll], js[kScanUnroll];
       float4 hv[kScanUnroll];
 #pragma unroll
       for (int u = 0; u < kScanUnroll; ++u) {
         const int w = base + 64 * u + lane;
         const int wc = w < total ? w : total - 1;
-        int lo = 0;  // largest candidate lane whose items start at or before item wc
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-          if (C.off[lo + step] <= wc) lo += step;
+        const int o1 = own1[wc - base];
+        const int lo = o1 > 0 ? o1 - 1 : 0;  // the candidate lane whose items hold item wc
         const int local = wc - C.off[lo];
         int jr = 0;  // that lane's range holding the item
 #pragma unroll
