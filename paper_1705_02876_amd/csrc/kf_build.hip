@@ -709,8 +709,9 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
   const float rzz = live ? float(pc[5]) + p.layer_vmax[2 * el + 1] : 0.f;
   const float fac = 1.f + p.margin;
   // plain half widths bound the chi2 < cut region (Cauchy-Schwarz on R^-1)
-  const float wt_plain = sqrtf(p.chi2_cut * rtt) * fac;
-  const float wz_plain = sqrtf(p.chi2_cut * rzz) * fac;
+  // (hardware square roots, within about an ulp: the margin covers far more)
+  const float wt_plain = __builtin_amdgcn_sqrtf(p.chi2_cut * rtt) * fac;
+  const float wz_plain = __builtin_amdgcn_sqrtf(p.chi2_cut * rzz) * fac;
   // Learned window: one network evaluation per live candidate, all lanes of the wave together.  Its box
   // (never wider than the plain one) decides which compatible hits count; when none is inside it, the
   // compatible hits of the plain window count instead (fallback).  One scan of the plain window's bins
@@ -747,9 +748,9 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
     C.need[lane] = tighter ? 1 : 0;  // cleared by the first pair inside the learned box
   }
   const float php = atan2f(py0, px0);
-  const float iR = 1.f / R;
+  const float iR = __builtin_amdgcn_rcpf(R);  // hardware reciprocals (about an ulp), inside the rows' widening
   const float emax = asinh_hw(p.g.z_half[l] * iR);
-  const float escale = static_cast<float>(p.n_eta) / (2.f * emax);
+  const float escale = static_cast<float>(p.n_eta) * __builtin_amdgcn_rcpf(2.f * emax);
   const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
   C.pred[0][lane] = ps[0];
   C.pred[1][lane] = ps[1];
@@ -1136,7 +1137,12 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       if (__ballot(kmin != ~0ull) == 0) break;  // no seed of the wave has a child left
       const int winner = gbase + key_parent(kmin);
       const int32_t wslot = __shfl(has_hit ? kids.slot_at(0) : -1, winner);
-      const T wchi2 = __shfl(has_hit ? kids.chi2_at(0) : chi2, winner);
+      // in single precision the key holds the child's chi2 exactly; in double precision it comes from the winner
+      T wchi2;
+      if constexpr (std::is_same<T, float>::value)
+        wchi2 = key_chi2(kmin);
+      else
+        wchi2 = __shfl(has_hit ? kids.chi2_at(0) : chi2, winner);
       if (kmin != ~0ull) {
         new_nc = r + 1;
         if (slot == r) {

@@ -52,7 +52,9 @@ KF_DEV float div_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 KF_DEV double div_t(double a, double b) { return a / b; }
 KF_DEV float atan_t(float x) { return atanf(x); }
 KF_DEV double atan_t(double x) { return atan(x); }
-KF_DEV float log_t(float x) { return logf(x); }
+// natural logarithm from the hardware base-2 logarithm (about an ulp; the one use, the Highland width's
+// logarithmic term, scales it by 0.038)
+KF_DEV float log_t(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
 KF_DEV double log_t(double x) { return log(x); }
 // Reciprocal and reciprocal square root of a positive, finite, normal value: the
 // hardware approximation refined by two Newton steps (each squares the relative

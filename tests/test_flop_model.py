@@ -27,6 +27,7 @@ def _host_header(dst):
     src = src.replace("__builtin_amdgcn_rcpf(x)", "1.0f / x")
     src = src.replace("__builtin_amdgcn_rcp(x)", "1.0 / x")
     src = src.replace("__builtin_amdgcn_rsq(x)", "1.0 / std::sqrt(x)")
+    src = src.replace("__builtin_amdgcn_logf(x)", "std::log2(x)")
     src = src.replace("__device__ __forceinline__", "static inline")
     src = src.replace("KF_DEV double copysign_t(double a, double b) { return copysign(a, b); }",
                       "KF_DEV double copysign_t(double a, double b) { return copysign(a, b); }\n"
