@@ -137,6 +137,48 @@ def test_fine_bin_grids_bit_exact(ctx, orc, n_phi, n_eta):
     assert np.array_equal(rec[:, :3], np.asarray(prob.hit_pos, np.float32)[perm])
 
 
+@pytest.mark.parametrize("n_phi,n_eta", [(1024, 32), (64, 16), (4096, 8)])
+def test_bins_of_hits_at_bin_edges(ctx, orc, n_phi, n_eta):
+    """Hits within a few 1e-7 of a phi or eta bin edge, where the single-precision estimate of the bin cannot
+    decide and the binning takes the double-precision definition: every hit's bin as the oracle's."""
+    import torch
+    from paper_1705_02876_amd import kfmi_build as KB
+    print(f"[bin edges {n_phi}x{n_eta}]", flush=True)
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    rng = np.random.default_rng(73)
+    L, per = det.n_layers, 3000
+    pos = []
+    for l in range(L):
+        R, zh = float(det32.radii[l]), float(np.broadcast_to(np.asarray(det32.z_half, np.float64), (L,))[l])
+        emax = np.arcsinh(zh / R)
+        kp = rng.integers(0, n_phi + 1, per)  # edges, including -pi and pi
+        ke = rng.integers(0, n_eta + 1, per)
+        phi = -np.pi + kp * (2 * np.pi / n_phi) + rng.uniform(-3e-7, 3e-7, per) * rng.choice([0.0, 1.0, 30.0], per)
+        eta = -emax + ke * (2 * emax / n_eta) + rng.uniform(-3e-7, 3e-7, per) * rng.choice([0.0, 1.0, 30.0], per)
+        # half the hits near a phi edge only, half near an eta edge only, a few near both
+        free_phi = rng.uniform(-np.pi, np.pi, per)
+        free_eta = rng.uniform(-emax, emax, per)
+        which = rng.integers(0, 3, per)
+        phi = np.where(which == 1, free_phi, phi)
+        eta = np.where(which == 0, free_eta, eta)
+        pos.append(np.stack([R * np.cos(phi), R * np.sin(phi), R * np.sinh(eta)], axis=1))
+    hit_pos = np.concatenate(pos).astype(np.float32)
+    n = hit_pos.shape[0]
+    offsets = np.arange(L + 1, dtype=np.int64) * per
+    cov = np.zeros((n, 6), np.float32)
+    cov[:, 0] = cov[:, 2] = 1e-4
+    cov[:, 5] = 1e-2
+    dev = "cuda"
+    bins = KB.bin_hits(ctx, torch.from_numpy(offsets).to(dev), torch.from_numpy(np.ascontiguousarray(hit_pos.T)).to(dev),
+                       torch.from_numpy(np.ascontiguousarray(cov.T)).to(dev), 1, n_phi=n_phi, n_eta=n_eta)
+    g = orc.geometry(det32)
+    bo, perm, _ = orc.bin_hits(g, 1, offsets, hit_pos.astype(np.float64), n_phi=n_phi, n_eta=n_eta)
+    assert np.array_equal(bins["bin_offsets"].cpu().numpy(), bo)
+    assert np.array_equal(bins["perm"].cpu().numpy()[:n].astype(np.int64), perm)
+
+
 @pytest.mark.parametrize("n_phi,n_eta,mode", [(512, 32, 1), (1024, 16, 0)])
 def test_build_independent_of_bin_grid(ctx, n_phi, n_eta, mode):
     """The window bounds the chi2 region, so the candidates do not depend on the bin grid."""
