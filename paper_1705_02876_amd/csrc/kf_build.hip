@@ -690,15 +690,60 @@ struct ChildList<float, Q> {
   }
 };
 
+// Plain window, single precision, grouped build: the list holds the children's rank keys of the merge itself
+// (nhits + 1, chi2 bits, parent slot, hit index).  Within one candidate nhits + 1 and the parent slot are fixed,
+// so the keys order as (chi2, index) do, and the merge takes the head key as it is.
+template <int Q>
+struct ChildListMerge {
+  uint64_t key[Q];  // empty: all ones
+  int32_t slot[Q];
+  uint64_t prefix;  // (63 - (nhits + 1)) << 58 | parent slot << 24
+  __device__ __forceinline__ void clear(int nhits_child, int parent) {
+    prefix = (static_cast<uint64_t>(63 - nhits_child) << 58) | (static_cast<uint64_t>(parent & 7) << 24);
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      key[t] = ~0ull;
+      slot[t] = 0;
+    }
+  }
+  __device__ __forceinline__ void insert(float nk, int32_t ni, int32_t nj, bool) {
+    const uint64_t nkey = prefix | (static_cast<uint64_t>(__float_as_uint(nk) & 0x7FFFFFFFu) << 27) |
+                          static_cast<uint32_t>(ni & 0xFFFFFF);
+    bool lt[Q];
+#pragma unroll
+    for (int t = 0; t < Q; ++t) lt[t] = nkey < key[t];
+#pragma unroll
+    for (int t = Q - 1; t >= 0; --t) {
+      const bool shift = t > 0 && lt[t - 1];
+      key[t] = shift ? key[t - 1] : (lt[t] ? nkey : key[t]);
+      slot[t] = shift ? slot[t - 1] : (lt[t] ? nj : slot[t]);
+    }
+  }
+  __device__ __forceinline__ float chi2_at(int t) const {
+    return __uint_as_float(static_cast<uint32_t>((key[t] >> 27) & 0x7FFFFFFFu));
+  }
+  __device__ __forceinline__ int32_t idx_at(int t) const { return static_cast<int32_t>(key[t] & 0xFFFFFFu); }
+  __device__ __forceinline__ int32_t slot_at(int t) const { return slot[t]; }
+  __device__ __forceinline__ void pop() {
+#pragma unroll
+    for (int t = 0; t + 1 < Q; ++t) {
+      key[t] = key[t + 1];
+      slot[t] = slot[t + 1];
+    }
+    key[Q - 1] = ~0ull;
+  }
+  __device__ __forceinline__ void strip_flags() {}
+};
+
 // Scans the plain window of this lane's candidate (the wave's 64 candidates together) and leaves in
 // kids the candidate's best children by (chi2, hit index): their accumulated chi2, hit index
 // within the (event, layer) and slot, cnt of them (at most N); with the learned window, the definition of the
 // learned search window with its fallback (see below).  Wave-uniform work counters are accumulated.
-template <int Q, typename T, bool LW>
+template <int Q, typename T, bool LW, typename List>
 __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, const unsigned char* mlp_lds, int l,
                                             int64_t el, bool live, const T (&ps)[6], const T (&pc)[21], float qf,
                                             T chi2, int N, int lane, uint64_t lanes_below, const float4* recs,
-                                            ChildList<T, Q>& kids, int& cnt,
+                                            List& kids, int& cnt,
                                             int& cnt_in, uint32_t& n_box, uint32_t& n_chi2, uint32_t& n_comp,
                                             uint32_t& n_fb) {
   // Window geometry of this lane's candidate (dead lanes only work for others).
@@ -1114,8 +1159,13 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       }
     }
     // ---- scan the window's bins, keep the best N children of this candidate
-    ChildList<T, G> kids;
-    kids.clear();
+    // the merge's own rank keys for the plain single-precision build (the head key is then the merge key)
+    constexpr bool kMergeKeys = std::is_same<T, float>::value && !LW;
+    std::conditional_t<kMergeKeys, ChildListMerge<G>, ChildList<T, G>> kids;
+    if constexpr (kMergeKeys)
+      kids.clear(nhits + 1, slot);
+    else
+      kids.clear();
     int cnt = 0;     // children in the list (at most N)
     int cnt_in = 0;  // learned window: those inside the learned box (at most N)
     scan_window<G, T, LW>(p, C, mlp_lds, l, el, active && pstat == 0, ps, pc, qf, chi2, N, lane, lanes_below, recs,
@@ -1129,8 +1179,12 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
     for (int r = 0; r < N; ++r) {
       uint64_t k = ~0ull;
       const bool has_hit = active && pstat == 0 && cnt > 0;
-      if (has_hit)
-        k = make_key(nhits + 1, float(kids.chi2_at(0)), slot, static_cast<uint32_t>(kids.idx_at(0)));
+      if (has_hit) {
+        if constexpr (kMergeKeys)
+          k = kids.key[0];
+        else
+          k = make_key(nhits + 1, float(kids.chi2_at(0)), slot, static_cast<uint32_t>(kids.idx_at(0)));
+      }
       else if (hole_left)
         k = make_key(nhits, float(chi2), slot, kHole);
       const uint64_t kmin = group_min<G>(k);
