@@ -472,7 +472,7 @@ void kf_graph_destroy(kf_graph* graph);
 
 /* kf_build_autotune: synchronous.  Times kf_build (cfg as given, args as
  * given, counters ignored) over the launch shapes {tiled, persistent,
- * serial} x waves_per_block {1, 2, 4} x blocks_per_cu {1, 2, 3, 4, 8}
+ * serial} x waves_per_block {1, 2, 4} x blocks_per_cu {1, 2, 3, 4, 8, 12, 14}
  * (persistent only, serial only, if args carries a large enough workspace;
  * serial only for the plain window in single precision), `reps` timed runs
  * each after one warm-up, and

@@ -1609,28 +1609,29 @@ template <int G, typename T, bool LW>
 __device__ __forceinline__ void persistent_body(const BuildP& p, int64_t n_tiles) {
   const unsigned char* wl = MlpLds<LW>::stage(p.mlp);
   const int lane = threadIdx.x & 63;
-  // The tile sequence is cut into kXcds contiguous chunks with a counter each.  Workgroups are dealt to the
-  // accelerator dies (XCDs) round robin, so a block takes tiles from the chunk of its die first, keeping each
-  // die's L2 on one stretch of events and directions, and then helps with the other chunks in turn.
+  // Each die has a counter and takes the tile sequence in runs of kXcdRun tiles, run r of die c being tiles
+  // [(r kXcds + c) kXcdRun, ... + kXcdRun), the runs the tiled launch deals to it: every die starts on the dense
+  // events (the sequence is ordered densest first) and works on neighbouring directions at a time, which share
+  // hit records in its L2.  Workgroups are dealt to the dies round robin, so a block serves its own die's runs
+  // first and then helps with the other dies' in turn.  A die's tiles increase with its counter, so the first
+  // index past the end means its runs are exhausted.
   // (one loop with a single call site of the tile body, so that the body is inlined once)
   const int home = static_cast<int>(blockIdx.x % kXcds);
   int k = 0, c = home;
-  int64_t lo = n_tiles * c / kXcds, hi = n_tiles * (c + 1) / kXcds;
 #pragma unroll 1
   for (;;) {
-    int32_t t = 0;
-    if (lane == 0) t = atomicAdd(&p.queue[c], 1);
-    t = __builtin_amdgcn_readfirstlane(t);
-    if (lo + t < hi) {
-      // the arguments are addressed through the tile number (t >> 31 is 0), so that their loads stay inside
+    int32_t j = 0;
+    if (lane == 0) j = atomicAdd(&p.queue[c], 1);
+    j = __builtin_amdgcn_readfirstlane(j);
+    const int64_t tile = ((static_cast<int64_t>(j) / kXcdRun) * kXcds + c) * kXcdRun + (j % kXcdRun);
+    if (tile < n_tiles) {
+      // the arguments are addressed through the counter value (j >> 31 is 0), so that their loads stay inside
       // the iteration instead of being held in registers across the loop
-      build_tile<G, T, LW>((&p)[t >> 31], lo + t, wl);
+      build_tile<G, T, LW>((&p)[j >> 31], tile, wl);
       continue;
     }
-    if (++k == kXcds) break;  // every chunk is exhausted
+    if (++k == kXcds) break;  // every die's runs are exhausted
     c = (home + k) % kXcds;
-    lo = n_tiles * c / kXcds;
-    hi = n_tiles * (c + 1) / kXcds;
   }
 }
 

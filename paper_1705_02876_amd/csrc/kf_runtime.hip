@@ -142,13 +142,13 @@ int32_t kf_build_autotune(kf_ctx* ctx, kf_build_cfg* cfg, const kf_build_args* a
   const bool can_serial = cfg->window_mode == KF_WINDOW_PLAIN && cfg->precision == KF_PREC_F32 && a.workspace &&
                           a.workspace_bytes >= kf_build_workspace_size(&sc, a.n_events, a.n_seeds);
   const int wpbs[3] = {1, 2, 4};
-  const int bpcs[5] = {1, 2, 3, 4, 8};
+  const int bpcs[7] = {1, 2, 3, 4, 8, 12, 14};  // 12 and 14 one-wave blocks fill a CU as the tiled launch does
   int32_t rc = KF_OK;
   for (int mode = KF_BUILD_TILED; mode <= KF_BUILD_SERIAL && rc == KF_OK; ++mode) {
     if (mode == KF_BUILD_PERSISTENT && !can_persist) continue;
     if (mode == KF_BUILD_SERIAL && !can_serial) continue;
     for (int wi = 0; wi < 3 && rc == KF_OK; ++wi)
-      for (int bi = 0; bi < (mode == KF_BUILD_PERSISTENT ? 5 : 1) && rc == KF_OK; ++bi) {
+      for (int bi = 0; bi < (mode == KF_BUILD_PERSISTENT ? 7 : 1) && rc == KF_OK; ++bi) {
         kf_build_cfg c = *cfg;
         c.mode = mode;
         c.waves_per_block = wpbs[wi];
