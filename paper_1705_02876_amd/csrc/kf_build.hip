@@ -117,22 +117,27 @@ __device__ __forceinline__ int hit_bin_fast(float x, float y, float z, const Bin
 // the largest pairs start first and the small ones fill in behind them (event sizes span a factor of 50; in
 // index order a large pair starting late holds the whole launch).  One block; the rank of each pair is counted
 // against every other pair, staged in LDS.  The result of the binning does not depend on the order.
+// kOrderThreads pairs per block, one per thread, the blocks on as many compute units (a single block had taken
+// 56 us, a twentieth of the binning, for 1088 pairs).
 constexpr int kOrderMax = 8192;
-__global__ void __launch_bounds__(1024) el_order_kernel(int32_t n_el, const int64_t* __restrict__ layer_offsets,
-                                                        int32_t* __restrict__ el_order) {
+constexpr int kOrderThreads = 256;
+__global__ void __launch_bounds__(kOrderThreads) el_order_kernel(int32_t n_el,
+                                                                 const int64_t* __restrict__ layer_offsets,
+                                                                 int32_t* __restrict__ el_order) {
   __shared__ int32_t sz[kOrderMax];
   for (int e = threadIdx.x; e < n_el; e += blockDim.x)
     sz[e] = static_cast<int32_t>(layer_offsets[e + 1] - layer_offsets[e]);
   __syncthreads();
-  for (int e = threadIdx.x; e < n_el; e += blockDim.x) {
-    const int32_t v = sz[e];
-    int rank = 0;
-    for (int f = 0; f < n_el; ++f) {
-      const int32_t w = sz[f];
-      rank += (w > v || (w == v && f < e)) ? 1 : 0;
-    }
-    el_order[rank] = e;
+  const int e = static_cast<int>(blockIdx.x) * kOrderThreads + static_cast<int>(threadIdx.x);
+  if (e >= n_el) return;
+  const int32_t v = sz[e];
+  int rank = 0;
+#pragma unroll 4
+  for (int f = 0; f < n_el; ++f) {
+    const int32_t w = sz[f];  // the same address in every lane: a broadcast read
+    rank += static_cast<int>((w > v) | ((w == v) & (f < e)));
   }
+  el_order[rank] = e;
 }
 
 __global__ void __launch_bounds__(kBinThreads) bin_kernel(int32_t L, const int64_t* __restrict__ layer_offsets,
@@ -1678,10 +1683,10 @@ __device__ __forceinline__ int seed_event_of(const int64_t* seed_offsets, int n_
 
 __device__ __forceinline__ int seed_cell(const float* __restrict__ st, int64_t ld, int64_t s) {
   const float x = st[s], y = st[ld + s], z = st[2 * ld + s];
-  const float r = sqrtf(x * x + y * y);
+  const float r2 = x * x + y * y;
   const float phi = atan2f(y, x);
-  const float eta = asinhf(z / r);
-  if (!(r > 0.f) || !isfinite(phi) || !isfinite(eta)) return 0;
+  const float eta = asinh_hw(z * __builtin_amdgcn_rsqf(r2));  // a cell of the tile order: any rounding will do
+  if (!(r2 > 0.f) || !isfinite(phi) || !isfinite(eta)) return 0;
   int ip = static_cast<int>((phi + 3.14159265f) * (kSeedPhi / 6.2831853f));
   int ie = static_cast<int>((eta + 2.f) * (kSeedEta / 4.f));
   ip = ip < 0 ? 0 : (ip > kSeedPhi - 1 ? kSeedPhi - 1 : ip);
@@ -1850,7 +1855,8 @@ int32_t kf_bin_hits(kf_ctx* ctx, const kf_bin_args* a) {
   int32_t* el_order = nullptr;  // index order beyond kOrderMax pairs
   if (n_el <= kOrderMax) {
     el_order = reinterpret_cast<int32_t*>(static_cast<char*>(a->workspace) + bin_ids_bytes(a->ldh));
-    el_order_kernel<<<1, 1024, 0, sm>>>(static_cast<int32_t>(n_el), a->layer_offsets, el_order);
+    el_order_kernel<<<static_cast<unsigned>((n_el + kOrderThreads - 1) / kOrderThreads), kOrderThreads, 0, sm>>>(
+        static_cast<int32_t>(n_el), a->layer_offsets, el_order);
     if (int32_t rc = kfh::check_hip(hipGetLastError(), "el_order_kernel launch")) return rc;
   }
   if (nb <= kMaxBins) {
