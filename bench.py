@@ -505,7 +505,7 @@ def main():
                     help="run a 1 GiB device copy first (calibrates HBM byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (the path does not shard across GPUs); --gpus must be 1"}))
         sys.exit(2)
 
     from paper_1705_02876_amd import synth as S, workloads as W
