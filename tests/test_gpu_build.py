@@ -228,6 +228,32 @@ def test_build_deterministic_and_modes_agree(ctx):
                 assert np.array_equal(a[k], d[k], equal_nan=True), ("serial", k)
 
 
+def test_persistent_runs_cover_every_tile(ctx):
+    """The persistent build hands each die runs of 256 tiles ((8 r + die) 256 onward): with about 2 100 tiles
+    (more than one run per die, the last run cut short) and with a few tiles (one die's run only), at one and
+    four waves per block, its outputs equal the tiled build's."""
+    import torch
+    from paper_1705_02876_amd import kfmi_build as KB
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    for counts, seed in (([7000, 7000, 7010], 74), ([40, 25], 75)):
+        prob = S.make_build_problem(counts, det, seed)
+        seeds, hits = KB.upload_problem(prob)
+        bins = KB.bin_hits(ctx, hits["layer_offsets"], hits["pos"], hits["cov"], prob.n_events)
+        res = []
+        for mode, wpb, bpc in ((KB.BUILD_TILED, 1, 0), (KB.BUILD_PERSISTENT, 1, 12), (KB.BUILD_PERSISTENT, 4, 3)):
+            cfg = KB.make_cfg(mode=mode, precision=KB.PREC_F32, waves_per_block=wpb, blocks_per_cu=bpc)
+            ws = torch.empty(KB.workspace_bytes(cfg, prob.n_events, seeds["n"]), dtype=torch.uint8, device="cuda")
+            out = KB.build(ctx, cfg, seeds, bins, hits["layer_offsets"], prob.n_events, workspace=ws)
+            torch.cuda.synchronize()
+            res.append({k: v.cpu().numpy() for k, v in out.items() if not k.startswith("_")})
+        print(f"[persistent runs] {sum(counts)} tracks, {seeds['n']} seeds", flush=True)
+        for r in res[1:]:
+            for k in res[0]:
+                assert np.array_equal(res[0][k], r[k], equal_nan=True), (counts, k)
+
+
 def test_build_edge_cases(ctx, orc):
     import torch
     det = S.detector_full()
