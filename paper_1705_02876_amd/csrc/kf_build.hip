@@ -554,8 +554,10 @@ __device__ __forceinline__ float wrap_pi(float a) {
 // hits, which are contiguous in the result list, into its register top-N.
 template <typename T, bool LW>
 struct ScanLds {
-  T pred[8][64];     // x, y, z, nx, ny, att, atz, azz: what the box test and a chi2 need of the candidate
-  float box[2][64];  // plain window half widths wt, wz
+  // per candidate lane: x, y, z, nx, ny, att, atz, azz (what the box test and a chi2 need of the candidate), and
+  // the plain window's half widths wt, wz; candidate-major, so that a reader takes them in two or three wide loads
+  alignas(16) T pred[64][8];
+  alignas(8) float box[64][2];
   int32_t off[64];                // exclusive prefix of the lanes' item counts
   int32_t rcum[kRangeChunk][64];  // per lane: items before each of its ranges
   int32_t rst[kRangeChunk][64];   // per lane: first slot of each of its ranges
@@ -802,16 +804,16 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
   const float emax = asinh_hw(p.g.z_half[l] * iR);
   const float escale = static_cast<float>(p.n_eta) * __builtin_amdgcn_rcpf(2.f * emax);
   const int32_t* bo = p.bin_offsets + el * (p.n_phi * p.n_eta + 1);
-  C.pred[0][lane] = ps[0];
-  C.pred[1][lane] = ps[1];
-  C.pred[2][lane] = ps[2];
-  C.pred[3][lane] = lp.nx;
-  C.pred[4][lane] = lp.ny;
-  C.pred[5][lane] = lp.att;
-  C.pred[6][lane] = lp.atz;
-  C.pred[7][lane] = lp.azz;
-  C.box[0][lane] = wt_plain;
-  C.box[1][lane] = wz_plain;
+  C.pred[lane][0] = ps[0];
+  C.pred[lane][1] = ps[1];
+  C.pred[lane][2] = ps[2];
+  C.pred[lane][3] = lp.nx;
+  C.pred[lane][4] = lp.ny;
+  C.pred[lane][5] = lp.att;
+  C.pred[lane][6] = lp.atz;
+  C.pred[lane][7] = lp.azz;
+  C.box[lane][0] = wt_plain;
+  C.box[lane][1] = wz_plain;
   // bins the plain window overlaps: the cyclic phi interval [ip0, ip0 + nspan) and the eta rows ie0..ie1
   int ip0 = 0, nspan = p.n_phi, ie0 = 0, ie1 = -1;
   if (live) {
@@ -876,17 +878,27 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
         const float mm[3] = {h.x, h.y, h.z};
         const float vv[6] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y};
         T pos3[6];
-        pos3[0] = C.pred[0][oq];
-        pos3[1] = C.pred[1][oq];
-        pos3[2] = C.pred[2][oq];
+        T pq[8];
+        if constexpr (std::is_same<T, float>::value) {  // two 16-byte LDS loads
+          const float4 q0 = *reinterpret_cast<const float4*>(&C.pred[oq][0]);
+          const float4 q1 = *reinterpret_cast<const float4*>(&C.pred[oq][4]);
+          pq[0] = q0.x; pq[1] = q0.y; pq[2] = q0.z; pq[3] = q0.w;
+          pq[4] = q1.x; pq[5] = q1.y; pq[6] = q1.z; pq[7] = q1.w;
+        } else {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) pq[k] = C.pred[oq][k];
+        }
+        pos3[0] = pq[0];
+        pos3[1] = pq[1];
+        pos3[2] = pq[2];
         LocalPred<T> L;
-        L.nx = C.pred[3][oq];
-        L.ny = C.pred[4][oq];
+        L.nx = pq[3];
+        L.ny = pq[4];
         L.tx = -L.ny;
         L.ty = L.nx;
-        L.att = C.pred[5][oq];
-        L.atz = C.pred[6][oq];
-        L.azz = C.pred[7][oq];
+        L.att = pq[5];
+        L.atz = pq[6];
+        L.azz = pq[7];
         if (!chi2_on_layer(pos3, L, mm, vv, c2) && c2 < T(p.chi2_cut)) {
           comp = true;
           hidx = __float_as_int(h.w) | (LW ? ((qo >> 6) << 30) : 0);
@@ -1024,10 +1036,26 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
         if (w < total) {
           const int o = own[u];
           // tangent (-ny, nx) at the prediction
-          const float dx = hv[u].x - float(C.pred[0][o]), dy = hv[u].y - float(C.pred[1][o]);
-          const float az = fabsf(hv[u].z - float(C.pred[2][o]));
-          const float at = fabsf(-float(C.pred[4][o]) * dx + float(C.pred[3][o]) * dy);
-          const bool plain_box = at <= C.box[0][o] && az <= C.box[1][o];
+          float px, py, pz, pnx, pny;
+          if constexpr (std::is_same<T, float>::value) {  // one 16-byte and one 4-byte LDS load
+            const float4 q = *reinterpret_cast<const float4*>(&C.pred[o][0]);
+            px = q.x;
+            py = q.y;
+            pz = q.z;
+            pnx = q.w;
+            pny = C.pred[o][4];
+          } else {
+            px = float(C.pred[o][0]);
+            py = float(C.pred[o][1]);
+            pz = float(C.pred[o][2]);
+            pnx = float(C.pred[o][3]);
+            pny = float(C.pred[o][4]);
+          }
+          const float2 bx = *reinterpret_cast<const float2*>(&C.box[o][0]);
+          const float dx = hv[u].x - px, dy = hv[u].y - py;
+          const float az = fabsf(hv[u].z - pz);
+          const float at = fabsf(-pny * dx + pnx * dy);
+          const bool plain_box = at <= bx.x && az <= bx.y;
           if (LW) {
             in_box = at <= C.lbox[0][o] && az <= C.lbox[1][o];
             out_box = !in_box && plain_box;
