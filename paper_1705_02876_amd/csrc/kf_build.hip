@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <type_traits>
 
@@ -578,11 +579,9 @@ struct ScanLds {
   // the plain window's half widths wt, wz; candidate-major, so that a reader takes them in two or three wide loads
   alignas(16) T pred[64][8];
   alignas(8) float box[64][2];
-  int32_t off[64];                // exclusive prefix of the lanes' item counts
-  int32_t rcum[kRangeChunk][64];  // per lane: items before each of its ranges
-  int32_t rst[kRangeChunk][64];   // per lane: first slot of each of its ranges
+  int32_t rbias[kRangeChunk][64];  // per lane and range: slot of an item of the range minus its flat item index
   int32_t q_slot[kQueueCap];
-  int32_t r_idx[64], r_slot[64];
+  int32_t r_idx[64], r_slot[64];  // during the scan: the 256 16-bit owner codes of a block of items
   T r_c2[64];
   int32_t cnt[64], rstart[64];  // compatible results per candidate in a batch, and where they start
   int32_t live_lane[64];        // compacted live candidates -> lane (window network)
@@ -988,51 +987,61 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
     }
   };
   // Ranges are taken kRangeChunk per lane at a time: their bounds load together, each lane's ranges are
-  // laid end to end (cumulative counts in LDS) and the lanes' totals end to end, so one flat item space
-  // covers them all.
+  // laid end to end and the lanes' totals end to end, so one flat item space covers them all; the slot of an
+  // item is its flat index plus its range's bias (in LDS).
   for (int r0 = 0; r0 < max_nr; r0 += kRangeChunk) {
     int ra[kRangeChunk], rn[kRangeChunk];
 #pragma unroll
     for (int j = 0; j < kRangeChunk; ++j) range_of(r0 + j, ra[j], rn[j]);
-    wave_lds_sync();  // the previous chunk's readers are done with the tables
     int mine = 0;
+    int cum[kRangeChunk];  // items of this lane before each of its ranges
 #pragma unroll
     for (int j = 0; j < kRangeChunk; ++j) {
-      C.rcum[j][lane] = mine;
-      C.rst[j][lane] = ra[j];
+      cum[j] = mine;
       mine += rn[j];
     }
     const int incl = wave_incl_scan<false>(mine);
     const int total = __builtin_amdgcn_readlane(incl, 63);
-    C.off[lane] = incl - mine;
+    const int my_off = incl - mine;  // flat index of this lane's first item
+    int first[kRangeChunk];          // flat index of the first item of each non-empty range (-1: empty)
+    wave_lds_sync();                 // the previous chunk's readers are done with the table
+#pragma unroll
+    for (int j = 0; j < kRangeChunk; ++j) {
+      C.rbias[j][lane] = ra[j] - (my_off + cum[j]);
+      first[j] = rn[j] > 0 ? my_off + cum[j] : -1;
+    }
     wave_lds_sync();
-    const int my_off = incl - mine;
-    int carry = 0;  // owner lane + 1 of the item before the current block of items (0: none)
+    int carry = 0;  // owner code of the item before the current block of items (0: none)
     for (int base = 0; base < total; base += 64 * kScanUnroll) {
       n_box += min(total - base, 64 * kScanUnroll);
-      // Owners of the block's 64 kScanUnroll items: each lane whose items start inside the block marks its first
-      // item with its lane + 1, and an item's owner is the largest mark at or before it, or the carry (lanes with
-      // items are in item order).  The marks sit in the batch result table, which is idle until the flush.
-      static_assert(64 * kScanUnroll == 256, "one byte of the 256-byte owner table per item");
-      uint32_t* const own4 = reinterpret_cast<uint32_t*>(C.r_idx);
-      const uint8_t* const own1 = reinterpret_cast<const uint8_t*>(C.r_idx);
+      // Owners of the block's 64 kScanUnroll items: the first item of each non-empty range (lane, j) is marked
+      // with the code lane * kRangeChunk + j + 1, and an item's owner code is the largest mark at or before it, or
+      // the carry (the ranges are laid out in code order).  The 16-bit codes sit in the batch result tables,
+      // which are idle until the flush.
+      static_assert(64 * kScanUnroll == 256, "one 16-bit owner code per item of a block");
+      static_assert(kRangeChunk == 4, "the owner code holds the range in its low two bits");
+      using Lds = ScanLds<T, LW>;
+      static_assert(offsetof(Lds, r_slot) == offsetof(Lds, r_idx) + 256, "the owner codes take r_idx and r_slot");
+      uint2* const own8 = reinterpret_cast<uint2*>(C.r_idx);
+      uint16_t* const own2 = reinterpret_cast<uint16_t*>(C.r_idx);
       wave_lds_sync();
-      own4[lane] = 0u;
+      own8[lane] = make_uint2(0u, 0u);
       wave_lds_sync();
-      if (mine > 0 && my_off >= base && my_off < base + 256)
-        reinterpret_cast<uint8_t*>(C.r_idx)[my_off - base] = static_cast<uint8_t>(lane + 1);
+#pragma unroll
+      for (int j = 0; j < kRangeChunk; ++j)
+        if (first[j] >= base && first[j] < base + 256)
+          own2[first[j] - base] = static_cast<uint16_t>(lane * kRangeChunk + j + 1);
       wave_lds_sync();
-      const uint32_t h4 = own4[lane];  // items base + 4 lane .. base + 4 lane + 3
-      const int m0 = static_cast<int>(h4 & 0xFFu), m1 = max(m0, static_cast<int>((h4 >> 8) & 0xFFu));
-      const int m2 = max(m1, static_cast<int>((h4 >> 16) & 0xFFu)), m3 = max(m2, static_cast<int>(h4 >> 24));
+      const uint2 h = own8[lane];  // items base + 4 lane .. base + 4 lane + 3
+      const int m0 = static_cast<int>(h.x & 0xFFFFu), m1 = max(m0, static_cast<int>(h.x >> 16));
+      const int m2 = max(m1, static_cast<int>(h.y & 0xFFFFu)), m3 = max(m2, static_cast<int>(h.y >> 16));
       const int sc = wave_incl_scan<true>(m3);  // inclusive maximum over the lanes
       const int before = max(wave_shift_up1(sc), carry);
-      const uint32_t ow = static_cast<uint32_t>(max(before, m0)) | (static_cast<uint32_t>(max(before, m1)) << 8) |
-                          (static_cast<uint32_t>(max(before, m2)) << 16) |
-                          (static_cast<uint32_t>(max(before, m3)) << 24);
+      const uint2 ow = make_uint2(static_cast<uint32_t>(max(before, m0)) | (static_cast<uint32_t>(max(before, m1)) << 16),
+                                  static_cast<uint32_t>(max(before, m2)) | (static_cast<uint32_t>(max(before, m3)) << 16));
       carry = max(carry, __builtin_amdgcn_readlane(sc, 63));
       wave_lds_sync();
-      own4[lane] = ow;  // the owners in item order
+      own8[lane] = ow;  // the owner codes in item order
       wave_lds_sync();
       int own[kScanUnroll], js[kScanUnroll];
       float4 hv[kScanUnroll];
@@ -1040,15 +1049,11 @@ __device__ __forceinline__ void scan_window(const BuildP& p, ScanLds<T, LW>& C, 
       for (int u = 0; u < kScanUnroll; ++u) {
         const int w = base + 64 * u + lane;
         const int wc = w < total ? w : total - 1;
-        const int o1 = own1[wc - base];
-        const int lo = o1 > 0 ? o1 - 1 : 0;  // the candidate lane whose items hold item wc
-        const int local = wc - C.off[lo];
-        int jr = 0;  // that lane's range holding the item
-#pragma unroll
-        for (int step = kRangeChunk / 2; step > 0; step >>= 1)
-          if (C.rcum[jr + step][lo] <= local) jr += step;
+        const int code = own2[wc - base];
+        const int c = code > 0 ? code - 1 : 0;
+        const int lo = c >> 2;  // the candidate lane whose range holds item wc
         own[u] = lo;
-        js[u] = C.rst[jr][lo] + (local - C.rcum[jr][lo]);
+        js[u] = wc + C.rbias[c & 3][lo];
         hv[u] = recs[static_cast<int64_t>(js[u]) * 3];
       }
 #pragma unroll
