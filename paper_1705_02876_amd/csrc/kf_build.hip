@@ -523,6 +523,38 @@ __device__ __forceinline__ uint64_t group_min(uint64_t k) {
   }
 }
 
+// Minimum of (k, s) by k over a seed group of six lanes (groups start at even lanes), the slot s travelling with its
+// key: the two lanes of a pair (lane, lane ^ 1) exchange by a DPP quad permutation, then every lane reads the pair
+// minima of the group's other two pairs, whose lanes' byte addresses are a1 and a2, in one round of LDS permutes.
+// Lanes past the last whole group (a1 = a2 = their own) get no minimum.
+__device__ __forceinline__ void group6_min(uint64_t& k, int32_t& s, int a1, int a2, bool in_group) {
+  constexpr int kSwapPairs = 0xB1;  // quad_perm [1, 0, 3, 2]
+  const uint32_t plo = static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(k)), kSwapPairs, 0xF, 0xF, true));
+  const uint32_t phi = static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(k >> 32)), kSwapPairs, 0xF, 0xF, true));
+  const int32_t ps = __builtin_amdgcn_update_dpp(0, s, kSwapPairs, 0xF, 0xF, true);
+  const uint64_t pk = (static_cast<uint64_t>(phi) << 32) | plo;
+  const bool take = pk < k;
+  k = take ? pk : k;
+  s = take ? ps : s;
+  const int lo = static_cast<int>(static_cast<uint32_t>(k)), hi = static_cast<int>(static_cast<uint32_t>(k >> 32));
+  const uint64_t k1 = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(a1, hi))) << 32) |
+                      static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(a1, lo));
+  const uint64_t k2 = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(a2, hi))) << 32) |
+                      static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(a2, lo));
+  const int32_t s1 = __builtin_amdgcn_ds_bpermute(a1, s), s2 = __builtin_amdgcn_ds_bpermute(a2, s);
+  if (k1 < k) {
+    k = k1;
+    s = s1;
+  }
+  if (k2 < k) {
+    k = k2;
+    s = s2;
+  }
+  if (!in_group) k = ~0ull;
+}
+
 __device__ __forceinline__ int phi_bin_f(float phi, int n_phi) {
   int b = static_cast<int>(floorf((phi + 3.14159265358979f) * (static_cast<float>(n_phi) * 0.159154943091895f)));
   return b < 0 ? 0 : (b > n_phi - 1 ? n_phi - 1 : b);
@@ -1236,6 +1268,11 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
     int32_t mine_slot = -1;
     T mine_chi2 = T(0);
     int new_nc = 0;
+    // six-lane groups: byte addresses of a lane in each of the other two pairs of the group
+    const int pair = slot >> 1;
+    const bool in_group = lane < SPW * G;
+    const int a1 = 4 * (in_group ? gbase + 2 * (pair == 2 ? 0 : pair + 1) : lane);
+    const int a2 = 4 * (in_group ? gbase + 2 * (pair == 0 ? 2 : pair - 1) : lane);
     for (int r = 0; r < N; ++r) {
       uint64_t k = ~0ull;
       const bool has_hit = active && pstat == 0 && cnt > 0;
@@ -1247,10 +1284,18 @@ __device__ void build_tile(const BuildP& p, int64_t tile, const unsigned char* m
       }
       else if (hole_left)
         k = make_key(nhits, float(chi2), slot, kHole);
-      const uint64_t kmin = group_min<G>(k);
+      uint64_t kmin;
+      int32_t wslot;
+      if constexpr (G == 6) {
+        kmin = k;
+        wslot = has_hit ? kids.slot_at(0) : -1;
+        group6_min(kmin, wslot, a1, a2, in_group);
+      } else {
+        kmin = group_min<G>(k);
+      }
       if (__ballot(kmin != ~0ull) == 0) break;  // no seed of the wave has a child left
       const int winner = gbase + key_parent(kmin);
-      const int32_t wslot = __shfl(has_hit ? kids.slot_at(0) : -1, winner);
+      if constexpr (G != 6) wslot = __shfl(has_hit ? kids.slot_at(0) : -1, winner);
       // in single precision the key holds the child's chi2 exactly; in double precision it comes from the winner
       T wchi2;
       if constexpr (std::is_same<T, float>::value)
