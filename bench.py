@@ -38,7 +38,7 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 #   per layer crossed: helix crossing, sparse Jacobian and J C J^T; per hit: local-frame chi2, gain, state
 #   and covariance update; per material layer: scattering and energy loss.  Square roots, reciprocal square
 #   roots, arctangents and logarithms (one to three per step) are not counted as FLOPs.
-FLOP_PER_LAYER = 638
+FLOP_PER_LAYER = 596
 FLOP_PER_HIT = 427
 FLOP_PER_MATERIAL = 85
 # one smoother step back from a layer: the filter's step repeated (material, crossing, transport) and the gain

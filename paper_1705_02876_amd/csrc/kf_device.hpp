@@ -84,6 +84,13 @@ KF_DEV float copysign_t(float a, float b) { return copysignf(a, b); }
 KF_DEV double copysign_t(double a, double b) { return copysign(a, b); }
 
 template <typename T>
+KF_DEV bool finite_n(const T* v, int n) {
+  T acc = T(0);
+  for (int i = 0; i < n; ++i) acc += v[i] * T(0);
+  return acc == T(0);
+}
+
+template <typename T>
 KF_DEV bool finite6_21(const T s[6], const T c[21]) {
   T acc = T(0);
 #pragma unroll
@@ -228,13 +235,16 @@ KF_DEV void transport(T c[21], const Prop<T>& p) {
   }
 }
 
-// Propagate + transport in place; on failure s and c are left unchanged.
+// Propagate + transport in place; on failure s and c are left unchanged.  A non-finite entry of the state or the
+// covariance gives ST_NONFINITE.  Only the state is checked before the crossing: a non-finite covariance entry
+// reaches the transported (z, z) entry (every entry of c enters row z of J c with a weight, and every entry of that
+// row enters (z, z)), so the check of the result finds it, and a failed crossing checks c before it reports.
 template <typename T>
 KF_DEV int32_t propagate(T s[6], T c[21], T a, T R, T zh) {
-  if (!finite6_21(s, c)) return ST_NONFINITE;
+  if (!finite_n(s, 6)) return ST_NONFINITE;
   Prop<T> p;
   int32_t st = helix_to_r(s, a, R, zh, p);
-  if (st) return st;
+  if (st) return finite_n(c, 21) ? st : ST_NONFINITE;
   T cn[21];
 #pragma unroll
   for (int k = 0; k < 21; ++k) cn[k] = c[k];
@@ -251,10 +261,10 @@ KF_DEV int32_t propagate(T s[6], T c[21], T a, T R, T zh) {
 // success, unspecified s and c on failure (no copy of the covariance is made).
 template <typename T>
 KF_DEV int32_t propagate_inplace(T s[6], T c[21], T a, T R, T zh) {
-  if (!finite6_21(s, c)) return ST_NONFINITE;
+  if (!finite_n(s, 6)) return ST_NONFINITE;
   Prop<T> p;
   const int32_t st = helix_to_r(s, a, R, zh, p);
-  if (st) return st;
+  if (st) return finite_n(c, 21) ? st : ST_NONFINITE;
   transport(c, p);
 #pragma unroll
   for (int k = 0; k < 6; ++k) s[k] = p.s[k];
