@@ -361,7 +361,9 @@ int32_t or_propagate(const or_geometry* g, int64_t n, double* state, double* cov
     memcpy(s, state + 6 * i, sizeof s);
     memcpy(C, cov + 36 * i, sizeof C);
     int32_t st = 0;
-    if (material_layer >= 0) st = material_impl(g, material_layer, s, C, NULL);
+    // a non-finite track is reported as such before any step, as in or_fit
+    if (material_layer >= 0)
+      st = (finite_n(s, 6) && finite_n(C, 36)) ? material_impl(g, material_layer, s, C, NULL) : OR_NONFINITE;
     if (!st) st = propagate_impl(g, s, C, q[i], r_target ? r_target[i] : r_scalar, z_half, NULL, NULL, NULL);
     if (!st) {
       memcpy(state + 6 * i, s, sizeof s);
