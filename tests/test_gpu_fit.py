@@ -152,6 +152,45 @@ def test_fit_rejects_bad_arguments(ctx):
     ctx.kf_set_geometry(det.as_float32())
 
 
+def test_propagate_nonfinite_statuses(ctx, orc):
+    """Statuses of the propagation for non-finite covariance entries, alone and with a crossing that fails (a
+    failed crossing still reports the non-finite input), and for non-finite states, equal to the oracle's."""
+    import torch
+    det = S.detector_full()
+    det32 = det.as_float32()
+    ctx.kf_set_geometry(det32)
+    g = orc.geometry(det32)
+    fp = S.make_fit_problem(40, det, 56)
+    tp, tm = fp.extra["true_pos"][3], fp.extra["true_mom"][3]
+    ok = np.flatnonzero(np.isfinite(tp[:, 0]))[:8]
+    s0 = np.concatenate([tp, tm], axis=1)[ok]
+    C0 = fp.cov0[ok].copy()
+    q = fp.q[ok]
+    C0[0, 4, 2] = C0[0, 2, 4] = np.nan        # non-finite covariance, crossing reached
+    C0[1, 5, 5] = np.inf                       # infinite variance, crossing reached
+    s0[2, 3:5] = [0.02, 0.0]                   # pT = 20 MeV: no crossing of the outer radius...
+    C0[2, 0, 0] = np.nan                       # ...and a non-finite covariance: non-finite wins
+    s0[3, 3:5] = [0.02, 0.0]                   # no crossing alone
+    s0[4, 1] = np.nan                          # non-finite state
+    s0[5, 3:5] = [0.02, 0.0]                   # no crossing with an infinite covariance entry
+    C0[5, 3, 1] = C0[5, 1, 3] = -np.inf
+    for material_layer in (-1, 3):
+        st_d = to_dev(soa_state(s0))
+        cv_d = to_dev(soa_cov(C0))
+        q_d = to_dev(q.astype(np.int8))
+        stat = torch.empty(len(ok), dtype=torch.int32, device="cuda")
+        ctx.kf_propagate_to_r(st_d, cv_d, q_d, stat, r_scalar=float(det32.radii[12]), z_half=float(det32.z_half),
+                              material_layer=material_layer)
+        torch.cuda.synchronize()
+        gst = stat.cpu().numpy()
+        _, _, ost = orc.propagate(g, rounded(s0), rounded(C0), q, r_scalar=det32.radii[12], z_half=det32.z_half,
+                                  material_layer=material_layer)
+        print(f"[propagate statuses] material {material_layer}: gpu {gst.tolist()} oracle {ost.tolist()}", flush=True)
+        assert np.array_equal(gst, ost)
+        assert gst[0] == gst[1] == gst[2] == gst[4] == gst[5] == 4
+        assert gst[3] == 1
+
+
 def test_propagate_parity(ctx, orc):
     import torch
     det = S.detector_full()
